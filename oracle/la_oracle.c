@@ -1,0 +1,289 @@
+/*
+ * FP64 CPU oracle for the FP32-accurate GEMM and the preconditioned
+ * Newton-Schulz polar factorisation of "Large Scale Distributed Linear
+ * Algebra With Tensor Processing Units" (arXiv 2112.09017).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It is deliberately plain and slow: every routine is
+ * the paper's definition or algorithm written out in double precision, with
+ * no blocking, fusion or reordering of the arithmetic.  It shares no code,
+ * header or constant with the GPU library.
+ *
+ * Conventions: real matrices, row-major with explicit leading dimension
+ * (element (i, j) of an R x C matrix X is X[i * ldx + j]).  The paper writes
+ * conjugate transposes; for real data they are plain transposes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* GEMM: eq. (Matmul), section III.A: C_ij = sum_k A_ik B_kj.               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * C <- alpha * op(A) op(B) + beta * C, op(X) = X or X^T.
+ * op(A) is m x k, op(B) is k x n, C is m x n.  Each output element is the
+ * dot product of row i of op(A) with column j of op(B), summed in k order.
+ * The operands are first copied to contiguous row/column buffers (a layout
+ * copy only; it changes no arithmetic) so that the dot products stream.
+ * beta == 0 means C is not read.
+ * Returns 0, or -1 if a buffer could not be allocated.
+ */
+int orc_gemm(int trans_a, int trans_b, int64_t m, int64_t n, int64_t k,
+             double alpha, const double *A, int64_t lda, const double *B,
+             int64_t ldb, double beta, double *C, int64_t ldc)
+{
+    double *ar = (double *)malloc(sizeof(double) * (size_t)(m * k + 1));
+    double *bc = (double *)malloc(sizeof(double) * (size_t)(n * k + 1));
+    if (!ar || !bc) {
+        free(ar);
+        free(bc);
+        return -1;
+    }
+    /* ar[i*k + p] = op(A)(i, p);  bc[j*k + p] = op(B)(p, j) */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = 0; p < k; ++p)
+            ar[i * k + p] = trans_a ? A[p * lda + i] : A[i * lda + p];
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t p = 0; p < k; ++p)
+            bc[j * k + p] = trans_b ? B[j * ldb + p] : B[p * ldb + j];
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0;
+            const double *x = ar + i * k;
+            const double *y = bc + j * k;
+            for (int64_t p = 0; p < k; ++p)
+                s += x[p] * y[p];
+            double c = alpha * s;
+            if (beta != 0.0)
+                c += beta * C[i * ldc + j];
+            C[i * ldc + j] = c;
+        }
+    }
+    free(ar);
+    free(bc);
+    return 0;
+}
+
+/* Frobenius norm, ||A||_F = sqrt(tr(A A^T)) (section III.D). */
+double orc_fro(int64_t m, int64_t n, const double *A, int64_t lda)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            s += A[i * lda + j] * A[i * lda + j];
+    return sqrt(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scalar maps of section III.D.                                            */
+/* ------------------------------------------------------------------------ */
+
+/* eq. (a_def): a = (3/2) sqrt(3) - s_minus */
+double orc_precond_a(double s_minus) { return 1.5 * sqrt(3.0) - s_minus; }
+
+/* eq. (RogueScalar): x -> a x (1 - (4/27) (a x)^2) */
+double orc_precond_map(double a, double x)
+{
+    return a * x * (1.0 - (4.0 / 27.0) * (a * x) * (a * x));
+}
+
+/* eq. (NS_scalar): x -> (1/2) x (3 - x^2) */
+double orc_ns_map(double x) { return 0.5 * x * (3.0 - x * x); }
+
+/*
+ * Number of preconditioning steps of Algorithm NS_Polar: feed the estimate
+ * s0 through eq. (RogueScalar) until it is no longer below s_minus.  The
+ * final value of s is written to *s_end (nullable).  Capped at 10000.
+ */
+int orc_precond_steps(double s0, double s_minus, double *s_end)
+{
+    double a = orc_precond_a(s_minus);
+    double s = s0;
+    int count = 0;
+    while (s < s_minus && count < 10000) {
+        s = orc_precond_map(a, s);
+        ++count;
+    }
+    if (s_end)
+        *s_end = s;
+    return count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Polar factorisation: Algorithm NS_Polar with eqs. (a_def)-(RogueMatrix)  */
+/* and (NewtonSchulz), section III.D.                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int iters_precond;  /* preconditioning steps taken                     */
+    int iters_ns;       /* Newton-Schulz steps taken                       */
+    double fro_norm_a;  /* ||A||_F                                          */
+    double last_delta;  /* ||U' - U||_F of the last Newton-Schulz step      */
+    int stop_reason;    /* 0 tolerance, 1 stagnation, 2 iteration cap       */
+} orc_polar_info;
+
+/*
+ * A is m x n (m >= n).  On return U (m x n, ldu) holds the polar factor and,
+ * if H is not NULL, H (n x n, ldh) holds (U^T A + A^T U) / 2.
+ *
+ * Steps, in the algorithm's order:
+ *   U <- A / ||A||_F
+ *   s <- s0;  a <- (3/2) sqrt(3) - s_minus
+ *   while s < s_minus:  s <- a s (1 - (4/27) a^2 s^2)
+ *                       U <- a U (I - (4/27) a^2 U^T U)
+ *   while delta > max(m, n) eps:  U' <- (1/2) U (3 I - U^T U)
+ *                                 delta <- ||U' - U||_F;  U <- U'
+ * Readings where the algorithm is silent: delta starts at +infinity (so at
+ * least one Newton-Schulz step runs); the loop also stops after max_iter
+ * steps, and, if stagnation != 0, when delta has fallen below 1e-2 sqrt(n)
+ * and then fails to halve from one step to the next (rounding noise floor).
+ * max_precond >= 0 caps the preconditioning loop (to inspect intermediate
+ * iterates); a negative value leaves it to the s-recurrence alone.
+ *
+ * Returns 0 on success, -1 on bad arguments or allocation failure, -2 if
+ * ||A||_F is zero or not finite.
+ */
+int orc_polar(int64_t m, int64_t n, const double *A, int64_t lda,
+              double s_minus, double s0, double eps, int max_precond,
+              int max_iter, int stagnation, double *U, int64_t ldu, double *H,
+              int64_t ldh, orc_polar_info *info)
+{
+    if (m < n || n < 1 || lda < n || ldu < n || (H && ldh < n))
+        return -1;
+    orc_polar_info loc;
+    memset(&loc, 0, sizeof loc);
+
+    double *X = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *Xn = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *G = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *T = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    if (!X || !Xn || !G || !T) {
+        free(X); free(Xn); free(G); free(T);
+        return -1;
+    }
+
+    /* U <- A / ||A||_F */
+    double fro = orc_fro(m, n, A, lda);
+    loc.fro_norm_a = fro;
+    if (!(fro > 0.0) || !isfinite(fro)) {
+        free(X); free(Xn); free(G); free(T);
+        if (info) *info = loc;
+        return -2;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            X[i * n + j] = A[i * lda + j] / fro;
+
+    /* preconditioning loop */
+    double a = orc_precond_a(s_minus);
+    double c = (4.0 / 27.0) * a * a;
+    double s = s0;
+    int pre_cap = max_precond >= 0 ? max_precond : 10000;
+    while (s < s_minus && loc.iters_precond < pre_cap) {
+        s = a * s * (1.0 - c * s * s);
+        /* G = U^T U */
+        orc_gemm(1, 0, n, n, m, 1.0, X, n, X, n, 0.0, G, n);
+        /* T = I - (4/27) a^2 G */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                T[i * n + j] = (i == j ? 1.0 : 0.0) - c * G[i * n + j];
+        /* U <- a U T */
+        orc_gemm(0, 0, m, n, n, a, X, n, T, n, 0.0, Xn, n);
+        double *t = X; X = Xn; Xn = t;
+        loc.iters_precond++;
+    }
+
+    /* Newton-Schulz loop */
+    double tol = (double)(m > n ? m : n) * eps;
+    double delta = INFINITY, prev = INFINITY;
+    loc.stop_reason = 2;
+    while (delta > tol) {
+        if (loc.iters_ns >= max_iter) {
+            loc.stop_reason = 2;
+            break;
+        }
+        /* G = U^T U;  T = 3 I - G;  U' = (1/2) U T */
+        orc_gemm(1, 0, n, n, m, 1.0, X, n, X, n, 0.0, G, n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                T[i * n + j] = (i == j ? 3.0 : 0.0) - G[i * n + j];
+        orc_gemm(0, 0, m, n, n, 0.5, X, n, T, n, 0.0, Xn, n);
+        /* delta = ||U' - U||_F */
+        double d2 = 0.0;
+        for (int64_t i = 0; i < m * n; ++i)
+            d2 += (Xn[i] - X[i]) * (Xn[i] - X[i]);
+        prev = delta;
+        delta = sqrt(d2);
+        double *t = X; X = Xn; Xn = t;
+        loc.iters_ns++;
+        if (delta <= tol) {
+            loc.stop_reason = 0;
+            break;
+        }
+        if (stagnation && delta < 1e-2 * sqrt((double)n) && delta > 0.5 * prev) {
+            loc.stop_reason = 1;
+            break;
+        }
+    }
+    loc.last_delta = delta;
+
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            U[i * ldu + j] = X[i * n + j];
+
+    if (H) {
+        /* H = (U^T A + A^T U) / 2 */
+        orc_gemm(1, 0, n, n, m, 1.0, X, n, A, lda, 0.0, G, n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                H[i * ldh + j] = 0.5 * (G[i * n + j] + G[j * n + i]);
+    }
+    free(X); free(Xn); free(G); free(T);
+    if (info) *info = loc;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2 x 2 closed form of the polar factor (eqs. PolarDecomp, SVDdef).        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For a real 2 x 2 A = [[a, b], [c, d]] of full rank, the orthogonal polar
+ * factor is the rotation (det A > 0) or reflection (det A < 0) nearest to A:
+ *   det > 0:  U = [[a + d, b - c], [c - b, a + d]] / sqrt((a + d)^2 + (b - c)^2)
+ *   det < 0:  U = [[a - d, b + c], [b + c, d - a]] / sqrt((a - d)^2 + (b + c)^2)
+ * (from Cayley-Hamilton: H^2 = A^T A and H = (A^T A + |det A| I) / tr H, so
+ * U = A H^-1 is A + sign(det A) adj(A)^T up to a positive factor), and
+ * H = U^T A.  Row-major in and out.  Returns -1 if det A == 0.
+ */
+int orc_polar_2x2(const double *A, double *U, double *H)
+{
+    double a = A[0], b = A[1], c = A[2], d = A[3];
+    double det = a * d - b * c;
+    double u00, u01, u10, u11, r;
+    if (det > 0.0) {
+        r = sqrt((a + d) * (a + d) + (b - c) * (b - c));
+        u00 = (a + d) / r; u01 = (b - c) / r;
+        u10 = (c - b) / r; u11 = (a + d) / r;
+    } else if (det < 0.0) {
+        r = sqrt((a - d) * (a - d) + (b + c) * (b + c));
+        u00 = (a - d) / r; u01 = (b + c) / r;
+        u10 = (b + c) / r; u11 = (d - a) / r;
+    } else {
+        return -1;
+    }
+    U[0] = u00; U[1] = u01; U[2] = u10; U[3] = u11;
+    if (H) {
+        H[0] = u00 * a + u10 * c;
+        H[1] = u00 * b + u10 * d;
+        H[2] = u01 * a + u11 * c;
+        H[3] = u01 * b + u11 * d;
+    }
+    return 0;
+}

@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each ``pin_*`` takes an ``oracle.Oracle`` instance and raises AssertionError
+if the oracle disagrees with something established independently of it: a
+number the paper states (``tests/golden/paper_claims.json``), a hand-derived
+closed form (``tests/golden/polar_2x2.json``), a textbook routine (numpy's
+SVD / float64 matmul / exact integer arithmetic), an exact construction
+A = Q diag(s) V^T, or an invariant of the polar factorisation.  The same pins
+run against builds of the oracle with planted mistakes
+(``test_oracle_mutants.py``) to show that they would catch them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+import la_inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _polar_svd(A):
+    """Polar factors from numpy's SVD (eq. SVDdef): U = U_s V_s^T, H = V_s S V_s^T."""
+    Us, S, Vt = np.linalg.svd(np.asarray(A, np.float64), full_matrices=False)
+    return Us @ Vt, (Vt.T * S[None, :]) @ Vt
+
+
+# --------------------------------------------------------------------------- scalar maps
+
+def pin_paper_iteration_counts(orc):
+    g = _golden("paper_claims.json")
+    c = g["precond_steps_single"]
+    k, s_end = orc.precond_steps(c["s0"], c["s_minus"])
+    assert c["min"] <= k <= c["max"], f"k_pre={k} outside the paper's {c['min']}-{c['max']}"
+    assert s_end >= c["s_minus"]
+
+    def ns_count(x, tol, cap=1000):
+        n = 0
+        while abs(1.0 - x) > tol and n < cap:
+            x = orc.ns_map(x)
+            n += 1
+        return n
+
+    c2 = g["ns_steps_from_0p1"]
+    k2 = ns_count(c2["x0"], c2["tol"])
+    assert abs(k2 - c2["approx"]) <= c2["slack"], f"NS from 0.1 took {k2}"
+    c3 = g["ns_steps_plain_small_s0"]
+    k3 = ns_count(c3["x0"], c3["tol"])
+    assert c3["min"] <= k3 <= c3["max"], f"plain NS from 1e-7 took {k3}"
+    c4 = g["total_iterations"]
+    total = k + ns_count(s_end, c2["tol"])
+    assert abs(total - c4["approx"]) <= c4["slack"], f"total {total}"
+
+
+def pin_scalar_map_properties(orc):
+    g = _golden("paper_claims.json")
+    # eq. (NS_scalar): 0 and 1 fixed, sqrt(3) -> 0, (0, sqrt 3) -> 1 under iteration
+    r3 = g["ns_stability_bound"]["value"]
+    assert orc.ns_map(0.0) == 0.0
+    assert orc.ns_map(1.0) == 1.0
+    assert abs(orc.ns_map(r3)) < 1e-15
+    for x0 in (1e-3, 0.3, 1.0, 1.5, 1.7):
+        x = x0
+        for _ in range(200):
+            x = orc.ns_map(x)
+        assert abs(x - 1.0) < 1e-14, (x0, x)
+    # eq. (RogueScalar): maximum over [0, 1] is exactly 1, at x = 3 / (2a)
+    # (calculus: p'(x) = a - (4/9) a^3 x^2 = 0); [s-, 1] maps into [s-, 1];
+    # values beneath s- are pushed up faster than by eq. (NS_scalar).
+    for sm in g["precond_keeps_above_s_minus"]["s_minus_values"]:
+        a = orc.precond_a(sm)
+        assert abs(a - (1.5 * math.sqrt(3.0) - sm)) < 1e-15
+        xs = 1.5 / a
+        assert abs(orc.precond_map(a, xs) - 1.0) < 1e-14
+        grid = np.linspace(sm, 1.0, 2001)
+        vals = np.array([orc.precond_map(a, x) for x in grid])
+        assert vals.min() >= sm - 1e-12, (sm, vals.min())
+        assert vals.max() <= 1.0 + 1e-12
+        for x in (1e-6, 1e-3, 0.5 * sm):
+            assert orc.precond_map(a, x) > orc.ns_map(x) > x
+
+
+# --------------------------------------------------------------------------- GEMM
+
+def pin_gemm_exact_integers(orc):
+    A = la_inputs.integer_matrix((37, 53), 11)
+    B = la_inputs.integer_matrix((53, 29), 12)
+    ref = A.astype(np.int64) @ B.astype(np.int64)
+    assert np.array_equal(orc.gemm(A, B), ref.astype(np.float64))
+    assert np.array_equal(orc.gemm(A.T.copy(), B, trans_a=True), ref)
+    assert np.array_equal(orc.gemm(A, B.T.copy(), trans_b=True), ref)
+    assert np.array_equal(orc.gemm(A.T.copy(), B.T.copy(), trans_a=True, trans_b=True), ref)
+    C0 = la_inputs.integer_matrix((37, 29), 13)
+    got = orc.gemm(A, B, alpha=2.0, beta=-3.0, C=C0)
+    assert np.array_equal(got, 2 * ref - 3 * C0.astype(np.int64))
+
+
+def pin_gemm_vs_numpy(orc):
+    A = la_inputs.gaussian((64, 96), 21)
+    B = la_inputs.gaussian((96, 80), 22)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    got = orc.gemm(A, B)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # identity and permutation
+    eye = np.eye(96)
+    assert np.array_equal(orc.gemm(A, eye), A.astype(np.float64))
+    perm = np.random.default_rng(3).permutation(80)
+    Pm = np.eye(80)[:, perm]
+    assert np.array_equal(orc.gemm(B, Pm), B.astype(np.float64)[:, perm])
+
+
+# --------------------------------------------------------------------------- polar
+
+def pin_polar_2x2_golden(orc):
+    for case in _golden("polar_2x2.json")["cases"]:
+        A = np.array(case["A"], np.float64)
+        if "U_times_sqrt5" in case:
+            Ue = np.array(case["U_times_sqrt5"]) / math.sqrt(5.0)
+            He = np.array(case["H_over_sqrt5"]) * math.sqrt(5.0)
+        elif "U_times_sqrt34" in case:
+            Ue = np.array(case["U_times_sqrt34"]) / math.sqrt(34.0)
+            He = np.array(case["H_times_sqrt34"]) / math.sqrt(34.0)
+        else:
+            Ue = np.array(case["U"], np.float64)
+            He = np.array(case["H"], np.float64)
+        Uc, Hc = orc.polar_2x2(A)
+        assert np.max(np.abs(Uc - Ue)) < 1e-14 and np.max(np.abs(Hc - He)) < 1e-13
+        U, H, info = orc.polar(A)
+        assert info.stop_reason == "tol", info
+        assert np.max(np.abs(U - Ue)) < 1e-13, (A, U, Ue)
+        assert np.max(np.abs(H - He)) < 1e-12, (A, H, He)
+
+
+def pin_polar_2x2_random_vs_svd(orc):
+    g = la_inputs.rng(31)
+    for _ in range(50):
+        A = g.standard_normal((2, 2))
+        Us, Hs = _polar_svd(A)
+        Uc, Hc = orc.polar_2x2(A)
+        assert np.max(np.abs(Uc - Us)) < 1e-9, (A, Uc, Us)
+        assert np.max(np.abs(Hc - Hs)) < 1e-9
+
+
+def pin_polar_block_embedding(orc):
+    """diag(B_1..B_k) conjugated by permutations has factors (P1 U P2, P2^T H P2)."""
+    g = la_inputs.rng(41)
+    k = 8
+    n = 2 * k
+    A = np.zeros((n, n))
+    Ue = np.zeros((n, n))
+    He = np.zeros((n, n))
+    for b in range(k):
+        blk = g.standard_normal((2, 2)) + (2.0 if b % 2 else -2.0) * np.eye(2)
+        ub, hb = orc.polar_2x2(blk)
+        sl = slice(2 * b, 2 * b + 2)
+        A[sl, sl] = blk
+        Ue[sl, sl] = ub
+        He[sl, sl] = hb
+    P1 = np.eye(n)[g.permutation(n)]
+    P2 = np.eye(n)[g.permutation(n)]
+    Ad = P1 @ A @ P2
+    U, H, info = orc.polar(Ad)
+    assert info.stop_reason in ("tol", "stagnation")
+    assert np.max(np.abs(U - P1 @ Ue @ P2)) < 1e-11
+    assert np.max(np.abs(H - P2.T @ He @ P2)) < 1e-11
+
+
+def pin_polar_exact_construction(orc):
+    """A = Q diag(s) V^T (float64) has U = Q V^T and H = V diag(s) V^T."""
+    for (m, n, lo) in ((48, 48, 1e-3), (80, 32, 1e-2)):
+        case = la_inputs.polar_case(m, n, lo, seeds=(51 + m, 52 + n, 53))
+        A = case.A64
+        U, H, info = orc.polar(A)
+        assert info.stop_reason in ("tol", "stagnation")
+        assert np.max(np.abs(U - case.U_exact)) < 1e-10
+        assert np.max(np.abs(H - case.H_exact)) < 1e-12
+
+
+def pin_polar_vs_numpy_svd(orc):
+    for (m, n, lo) in ((64, 64, 1e-4), (96, 40, 1e-3)):
+        case = la_inputs.polar_case(m, n, lo, seeds=(61 + m, 62, 63 + n))
+        A = case.A32.astype(np.float64)
+        Us, Hs = _polar_svd(A)
+        U, H, info = orc.polar(A)
+        assert np.linalg.norm(U - Us) < 1e-9
+        assert np.linalg.norm(H - Hs) < 1e-12 * np.linalg.norm(A) * 10
+
+
+def pin_polar_invariants(orc):
+    case = la_inputs.polar_case(72, 56, 1e-5, seeds=(71, 72, 73))
+    A = case.A32.astype(np.float64)
+    U, H, info = orc.polar(A)
+    n = A.shape[1]
+    assert np.linalg.norm(U.T @ U - np.eye(n)) / math.sqrt(n) < 1e-13
+    assert np.array_equal(H, H.T)
+    assert np.linalg.eigvalsh(H).min() > -1e-12
+    assert np.linalg.norm(A - U @ H) / np.linalg.norm(A) < 1e-13
+    assert info.iters_precond == orc.precond_steps(2.0 ** -52, 0.1)[0]
+
+
+def pin_polar_matrix_steps_act_on_singular_values(orc):
+    """eqs. (odd_power), (RogueMatrix), (NewtonSchulz): each matrix step maps the
+    singular values of the iterate by its scalar polynomial and keeps the
+    singular vectors."""
+    case = la_inputs.polar_case(40, 24, 1e-3, seeds=(81, 82, 83))
+    A = case.A64
+    sig = np.sort(case.s)[::-1] / np.linalg.norm(A)
+    a = 1.5 * math.sqrt(3.0) - 0.1
+    for kpre in (0, 1, 3, 6):
+        X, _, info = orc.polar(A, max_precond=kpre, max_iter=0, want_h=False)
+        assert info.iters_precond == kpre
+        s_exp = sig.copy()
+        for _ in range(kpre):
+            s_exp = a * s_exp * (1.0 - (4.0 / 27.0) * a * a * s_exp ** 2)
+        sv = np.linalg.svd(X, compute_uv=False)
+        assert np.max(np.abs(np.sort(sv) - np.sort(s_exp))) < 1e-13, kpre
+        # singular vectors unchanged: X V = Q diag(s_exp) up to sorting
+        XV = X @ case.V
+        col = np.linalg.norm(XV, axis=0)
+        ratio = XV / col[None, :]
+        assert np.max(np.abs(np.abs(np.sum(ratio * case.Q, axis=0)) - 1.0)) < 1e-10
+    for kns in (1, 2, 4):
+        kpre = 3
+        X, _, info = orc.polar(A, max_precond=kpre, max_iter=kns, want_h=False,
+                               stagnation=False)
+        assert info.iters_ns == kns
+        s_exp = sig.copy()
+        for _ in range(kpre):
+            s_exp = a * s_exp * (1.0 - (4.0 / 27.0) * a * a * s_exp ** 2)
+        for _ in range(kns):
+            s_exp = 0.5 * s_exp * (3.0 - s_exp ** 2)
+        sv = np.linalg.svd(X, compute_uv=False)
+        assert np.max(np.abs(np.sort(sv) - np.sort(s_exp))) < 1e-13, kns
+
+
+def pin_polar_special_cases(orc):
+    g = la_inputs.rng(91)
+    Qh = la_inputs.haar(20, 92)
+    U, H, _ = orc.polar(Qh)                      # orthogonal -> (A, I)
+    assert np.max(np.abs(U - Qh)) < 1e-13 and np.max(np.abs(H - np.eye(20))) < 1e-13
+    d = np.exp(g.uniform(-3, 0, size=20))
+    U, H, _ = orc.polar(np.diag(d))              # positive diagonal -> (I, A)
+    assert np.max(np.abs(U - np.eye(20))) < 1e-13 and np.max(np.abs(H - np.diag(d))) < 1e-13
+    U, H, _ = orc.polar(3.5 * np.eye(7))         # c I -> (I, c I)
+    assert np.max(np.abs(U - np.eye(7))) < 1e-14 and np.max(np.abs(H - 3.5 * np.eye(7))) < 1e-13
+    U, H, _ = orc.polar(np.array([[-2.5]]))      # 1 x 1 -> (sign a, |a|)
+    assert abs(U[0, 0] + 1.0) < 1e-15 and abs(H[0, 0] - 2.5) < 1e-14
+    # transposition: polar(A^T) = (U^T, U H U^T) for square A
+    A = la_inputs.polar_case(24, 24, 1e-2, seeds=(93, 94, 95)).A64
+    U, H, _ = orc.polar(A)
+    Ut, Ht, _ = orc.polar(A.T.copy())
+    assert np.max(np.abs(Ut - U.T)) < 1e-12
+    assert np.max(np.abs(Ht - U @ H @ U.T)) < 1e-12
+
+
+def pin_polar_scale_invariance(orc):
+    A = la_inputs.polar_case(32, 24, 1e-2, seeds=(96, 97, 98)).A32.astype(np.float64)
+    U, H, _ = orc.polar(A)
+    for k in (-7, 5):
+        Uk, Hk, _ = orc.polar(A * 2.0 ** k)
+        assert np.array_equal(Uk, U)
+        assert np.array_equal(Hk, H * 2.0 ** k)
+
+
+def pin_polar_rank_deficient(orc):
+    """NS sends singular value 0 to 0 (eq. NS_scalar): U is a partial isometry.
+    Run without preconditioning (s0 = s-), which would amplify rounding noise
+    in the null space."""
+    g = la_inputs.rng(99)
+    n, r = 16, 11
+    Q = la_inputs.haar(n, 100)
+    V = la_inputs.haar(n, 101)
+    s = np.zeros(n)
+    s[:r] = g.uniform(0.5, 1.0, size=r)
+    A = (Q * s[None, :]) @ V.T
+    U, H, info = orc.polar(A, s0=0.1)
+    assert info.iters_precond == 0
+    assert np.max(np.abs(U @ U.T @ U - U)) < 1e-11
+    assert np.max(np.abs(A - U @ H)) < 1e-12
+    assert np.max(np.abs(U - Q[:, :r] @ V[:, :r].T)) < 1e-11
+
+
+ALL_PINS = [
+    pin_paper_iteration_counts,
+    pin_scalar_map_properties,
+    pin_gemm_exact_integers,
+    pin_gemm_vs_numpy,
+    pin_polar_2x2_golden,
+    pin_polar_2x2_random_vs_svd,
+    pin_polar_block_embedding,
+    pin_polar_exact_construction,
+    pin_polar_vs_numpy_svd,
+    pin_polar_invariants,
+    pin_polar_matrix_steps_act_on_singular_values,
+    pin_polar_special_cases,
+    pin_polar_scale_invariance,
+    pin_polar_rank_deficient,
+]

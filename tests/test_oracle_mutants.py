@@ -1,0 +1,63 @@
+"""Planted mistakes in the oracle must each fail at least one pin (no GPU).
+
+Each mutant is a copy of ``oracle/la_oracle.c`` with one plausible slip (a
+dropped term, a wrong sign, constant or index, a transposed operand), built
+with gcc into a temporary directory and run through every pin in ``pins``.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "la_oracle.c")
+
+MUTANTS = {
+    "precond_constant": ("double c = (4.0 / 27.0) * a * a;", "double c = (4.0 / 9.0) * a * a;"),
+    "precond_sign": ("(i == j ? 1.0 : 0.0) - c * G[i * n + j]", "(i == j ? 1.0 : 0.0) + c * G[i * n + j]"),
+    "precond_drop_a": ("orc_gemm(0, 0, m, n, n, a, X, n, T, n, 0.0, Xn, n);",
+                       "orc_gemm(0, 0, m, n, n, 1.0, X, n, T, n, 0.0, Xn, n);"),
+    "a_def_sign": ("return 1.5 * sqrt(3.0) - s_minus;", "return 1.5 * sqrt(3.0) + s_minus;"),
+    "ns_three": ("(i == j ? 3.0 : 0.0) - G[i * n + j]", "(i == j ? 2.0 : 0.0) - G[i * n + j]"),
+    "ns_half": ("orc_gemm(0, 0, m, n, n, 0.5, X, n, T, n, 0.0, Xn, n);",
+                "orc_gemm(0, 0, m, n, n, 1.0, X, n, T, n, 0.0, Xn, n);"),
+    "gram_transposed": ("orc_gemm(1, 0, n, n, m, 1.0, X, n, X, n, 0.0, G, n);\n        /* T = I",
+                        "orc_gemm(0, 1, n, n, n, 1.0, X, n, X, n, 0.0, G, n);\n        /* T = I"),
+    "no_fro_scaling": ("X[i * n + j] = A[i * lda + j] / fro;", "X[i * n + j] = A[i * lda + j];"),
+    "delta_sign": ("d2 += (Xn[i] - X[i]) * (Xn[i] - X[i]);", "d2 += (Xn[i] + X[i]) * (Xn[i] + X[i]);"),
+    "h_not_symmetrised": ("0.5 * (G[i * n + j] + G[j * n + i])", "G[i * n + j]"),
+    "gemm_trans_a_index": ("trans_a ? A[p * lda + i] : A[i * lda + p]", "trans_a ? A[i * lda + p] : A[i * lda + p]"),
+    "gemm_drop_beta": ("c += beta * C[i * ldc + j];", "c += 0.0;"),
+    "fro_missing_sqrt": ("    return sqrt(s);\n}", "    return s;\n}"),
+    "closed_form_sign": ("u10 = (c - b) / r; u11 = (a + d) / r;", "u10 = (b - c) / r; u11 = (a + d) / r;"),
+    "scalar_map_const": ("return 0.5 * x * (3.0 - x * x);", "return 0.5 * x * (3.0 - 0.9 * x * x);"),
+    "precond_steps_off_by_one": ("    while (s < s_minus && count < 10000) {", "    while (s <= 2 * s_minus && count < 10000) {"),
+}
+
+
+@pytest.fixture(scope="module")
+def src_text():
+    with open(SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, src_text, tmp_path):
+    old, new = MUTANTS[name]
+    assert src_text.count(old) == 1, f"mutation anchor for {name} not unique/present"
+    mutated = src_text.replace(old, new)
+    c_path = tmp_path / "mut.c"
+    c_path.write_text(mutated)
+    so = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                    "-ffp-contract=off", str(c_path), "-o", str(so), "-lm"], check=True)
+    orc = oracle.Oracle(str(so))
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(orc)
+        except Exception as e:  # noqa: BLE001 - any failure of a pin counts
+            failed.append((pin.__name__, type(e).__name__))
+    assert failed, f"mutant {name} passed every pin"
