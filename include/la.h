@@ -1,0 +1,203 @@
+/*
+ * la.h -- C ABI of the MI355X (gfx950) FP32-accurate GEMM and Newton-Schulz
+ * polar factorisation library.
+ *
+ * The operations follow "Large Scale Distributed Linear Algebra With Tensor
+ * Processing Units" (arXiv 2112.09017):
+ *   la_gemm   -- C = A B (section III, task list; eq. (Matmul) of III.A), with
+ *                transposed operands (III.A: SUMMA handles transposes);
+ *   la_polar  -- A = U H for an (M, N) A with M >= N, U with orthonormal
+ *                columns and H positive semi-definite (eq. (PolarDecomp),
+ *                III.D), computed by the preconditioned Newton-Schulz
+ *                iteration of Algorithm NS_Polar (eqs. (a_def)-(RogueMatrix),
+ *                (NewtonSchulz));
+ *   la_serve_* -- a continuous-batching server of la_polar requests.
+ *
+ * Conventions (the paper is silent on all of them):
+ *   - real FP32 data, ROW-MAJOR with explicit leading dimensions: element
+ *     (i, j) of X with leading dimension ldx is X[i * ldx + j];
+ *   - every matrix pointer passed to la_gemm / la_polar is DEVICE memory
+ *     owned by the caller; the library never frees or retains it;
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream); la_gemm
+ *     only enqueues work, la_polar blocks on a per-iteration 8-byte readback;
+ *   - no exceptions cross the ABI and nothing aborts: every call returns a
+ *     la_status; la_last_error() gives a message for the calling thread.
+ */
+#ifndef LA_H
+#define LA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LA_OK = 0,
+    LA_ERR_INVALID_ARG = 1,    /* null pointer, bad enum, aliasing, ...          */
+    LA_ERR_SHAPE = 2,          /* negative size, ld < row length, M < N (polar)  */
+    LA_ERR_NONFINITE = 3,      /* ||A||_F or a step norm is Inf/NaN, or A == 0   */
+    LA_ERR_NOT_CONVERGED = 4,  /* polar hit max_iter without reaching tolerance  */
+    LA_ERR_OUT_OF_MEMORY = 5,  /* workspace / arena smaller than required        */
+    LA_ERR_DEVICE = 6,         /* HIP runtime error or unsupported device        */
+    LA_ERR_QUEUE_FULL = 7,     /* serving queue at capacity                      */
+    LA_ERR_TOO_LARGE = 8,      /* request footprint exceeds the serving arena    */
+    LA_ERR_NOT_READY = 9,      /* serving request still pending                  */
+    LA_ERR_UNKNOWN_REQUEST = 10
+} la_status;
+
+/* Arithmetic of the GEMM products.  All paths read and write FP32 and
+ * accumulate in FP32 on the matrix cores.
+ *   FP32   : v_mfma_f32_32x32x2_f32 on the FP32 operands.
+ *   BF16X3 : each operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+ *            (round to nearest even); products hi*hi + hi*lo + lo*hi on the
+ *            BF16 matrix cores (each product exact in FP32).
+ *   BF16X6 : x = hi + mid + lo (three bf16 terms, 24 significant bits);
+ *            products hh + hm + mh + mm + hl + lh.
+ *   AUTO   : la_gemm -> BF16X3; la_polar -> per phase (see la_polar_opts).
+ * The paper's TPU "fp32" matmul is itself a bf16-based emulation at about
+ * six times the bf16 cost (section II); BF16X6 is the analogue here. */
+typedef enum {
+    LA_PREC_AUTO = 0,
+    LA_PREC_FP32 = 1,
+    LA_PREC_BF16X3 = 2,
+    LA_PREC_BF16X6 = 3
+} la_precision;
+
+typedef struct la_context la_context;
+
+/* Create a context on HIP device `device` (must be gfx950).  Allocates no
+ * device memory.  *out is set only on LA_OK. */
+la_status la_create(int device, la_context **out);
+/* Destroy a context (NULL is accepted).  Does not synchronise any stream. */
+la_status la_destroy(la_context *ctx);
+
+/* Static text for a status code (never NULL). */
+const char *la_status_string(la_status s);
+/* Message describing the last failed call made by this thread ("" if none).
+ * Valid until the next library call on this thread. */
+const char *la_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * GEMM (section III.A, eq. (Matmul)):  C <- alpha op(A) op(B) + beta C
+ *   op(A) is m x k: A is m x k (lda >= k) if trans_a == 0, else k x m
+ *                   (lda >= m);
+ *   op(B) is k x n: B is k x n (ldb >= n) if trans_b == 0, else n x k
+ *                   (ldb >= k);
+ *   C is m x n (ldc >= n) and must not overlap A or B.
+ * beta == 0 means C is not read (it may hold NaN).  m, n, k may be 0
+ * (k == 0 gives C <- beta C).  Enqueued on hip_stream; returns without
+ * waiting.  Arguments are validated before any device call.
+ * ---------------------------------------------------------------------- */
+la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m,
+                  int64_t n, int64_t k, float alpha, const float *A,
+                  int64_t lda, const float *B, int64_t ldb, float beta,
+                  float *C, int64_t ldc, la_precision prec, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Polar factorisation (section III.D, Algorithm NS_Polar).
+ * ---------------------------------------------------------------------- */
+
+/* Options; a zero-initialised struct means the defaults in brackets. */
+typedef struct {
+    double s_minus;   /* threshold s_- of eq. (a_def)                   [0.1]   */
+    double s0;        /* estimate of the smallest singular value of
+                         A / ||A||_F; fixes the preconditioning count     [2^-23] */
+    double eps;       /* tolerance: stop once ||U' - U||_F <= max(M,N) eps [2^-23] */
+    int max_iter;     /* cap on Newton-Schulz steps                     [100]   */
+    int prec_precond; /* la_precision of the preconditioning GEMMs [AUTO=BF16X6] */
+    int prec_ns;      /* la_precision of the Newton-Schulz GEMMs   [AUTO=BF16X3] */
+    int prec_h;       /* la_precision of H = sym(U^T A)            [AUTO=BF16X3] */
+    int polish;       /* 1: one extra Newton-Schulz step at BF16X6 after the
+                         stop test                                          [0] */
+    int no_stagnation;/* 1: disable the stagnation stop                     [0] */
+    int reserved[3];
+} la_polar_opts;
+
+typedef struct {
+    int iters_precond;   /* preconditioning steps (from the s recurrence)     */
+    int iters_ns;        /* Newton-Schulz steps, polish included              */
+    double fro_norm_a;   /* ||A||_F, accumulated in FP64 on the GPU            */
+    double last_delta;   /* ||U' - U||_F of the last step (FP64)               */
+    int stop_reason;     /* 0 tolerance, 1 stagnation, 2 iteration cap        */
+    int prec_precond;    /* resolved precisions actually used                 */
+    int prec_ns;
+    int prec_h;
+} la_polar_info;
+
+/* Bytes of device workspace la_polar needs for an m x n input (0 on bad
+ * arguments).  opts may be NULL. */
+size_t la_polar_workspace_size(int64_t m, int64_t n, const la_polar_opts *opts);
+
+/* A (m x n, lda >= n, m >= n >= 1) is read only.  U (m x n, ldu >= n)
+ * receives the polar factor; H (n x n, ldh >= n) receives
+ * (U^T A + A^T U) / 2 (the paper's H = U^T A, symmetrised) unless H is NULL.
+ * U and H must not overlap A, each other or the workspace.
+ * workspace: device memory of at least la_polar_workspace_size() bytes,
+ * 256-byte aligned.  Runs on hip_stream and returns after the last kernel
+ * has completed (it reads one FP64 norm back per iteration).
+ * LA_ERR_NONFINITE if ||A||_F is 0, Inf or NaN, or a step norm is not
+ * finite; LA_ERR_NOT_CONVERGED if the cap was hit (U then holds the last
+ * iterate).  info may be NULL. */
+la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A,
+                   int64_t lda, float *U, int64_t ldu, float *H, int64_t ldh,
+                   void *workspace, size_t ws_bytes, const la_polar_opts *opts,
+                   la_polar_info *info, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of polar requests.
+ * Requests are admitted while their device footprint fits the arena and a
+ * slot is free; every tick advances all active requests by one iteration
+ * with grouped launches (one Gram launch and one update launch for all of
+ * them), so requests of different sizes and phases share the GPU.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int max_slots;     /* requests in flight at once                    [32]   */
+    int max_queue;     /* requests waiting for admission                [4096] */
+    int reserved[6];
+} la_serve_config;
+
+typedef struct {
+    uint64_t submitted, completed, failed, ticks;
+    int active, queued;
+    double busy_seconds;   /* host wall time spent inside ticks            */
+    size_t arena_high_water;
+} la_serve_stats;
+
+typedef struct la_server la_server;
+
+/* arena: caller-owned device memory (256-byte aligned) the server carves
+ * request state from; it is not freed by the library.  cfg may be NULL.
+ * Starts one scheduler thread bound to ctx's device. */
+la_status la_serve_create(la_context *ctx, const la_serve_config *cfg,
+                          void *arena, size_t arena_bytes, la_server **out);
+
+/* Queue a polar of the m x n HOST matrix A_host (row-major, lda >= n).  A
+ * is copied before the call returns.  LA_ERR_TOO_LARGE if the request could
+ * never fit the arena; LA_ERR_QUEUE_FULL if the queue is at capacity.
+ * opts may be NULL. *req_id receives a handle (unique per server). */
+la_status la_serve_submit(la_server *srv, int64_t m, int64_t n,
+                          const float *A_host, int64_t lda,
+                          const la_polar_opts *opts, uint64_t *req_id);
+
+/* Non-blocking.  LA_ERR_NOT_READY while the request is pending.  Once it is
+ * done, copies U (m x n, row-major, contiguous) and, if H_host is not NULL,
+ * H (n x n) to host memory, fills *info (nullable), stores the request's
+ * own status in *req_status and forgets the request (a second poll returns
+ * LA_ERR_UNKNOWN_REQUEST). */
+la_status la_serve_poll(la_server *srv, uint64_t req_id, float *U_host,
+                        float *H_host, la_polar_info *info,
+                        la_status *req_status);
+
+la_status la_serve_stats_get(la_server *srv, la_serve_stats *out);
+
+/* Stops the scheduler (pending requests are cancelled) and frees host
+ * state.  NULL is accepted. */
+la_status la_serve_destroy(la_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LA_H */

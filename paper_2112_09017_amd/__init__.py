@@ -1,0 +1,104 @@
+"""MI355X (gfx950) FP32-accurate GEMM and Newton-Schulz polar factorisation.
+
+Python face of the C ABI in ``include/la.h`` (arXiv 2112.09017, sections III.A
+and III.D).  Tensors are torch float32 CUDA (HIP) tensors; a 2-D tensor whose
+last stride is 1 is passed as a row-major matrix, one whose first stride is 1
+as the transpose of one (so ``A.T`` costs nothing).  All arithmetic runs in the
+library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._binding import (LAError, PolarInfo, PolarOpts, Precision, ServeConfig, ServeStats,
+                       Status, check, context, lib, make_opts, LIB_PATH, SIGNATURES)
+
+__all__ = ["gemm", "polar", "polar_workspace_size", "Precision", "LAError", "Status",
+           "lib", "LIB_PATH", "Server"]
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_matrix(t: torch.Tensor, name: str):
+    """(pointer, rows, cols, ld, transposed) of a 2-D float32 device tensor."""
+    if t.dtype != torch.float32 or t.dim() != 2 or not t.is_cuda:
+        raise TypeError(f"{name} must be a 2-D float32 GPU tensor")
+    r, c = t.shape
+    s0, s1 = t.stride()
+    if s1 == 1 and (s0 >= max(c, 1) or r <= 1):
+        return t.data_ptr(), r, c, max(s0, c, 1), False
+    if s0 == 1 and (s1 >= max(r, 1) or c <= 1):
+        return t.data_ptr(), r, c, max(s1, r, 1), True
+    raise ValueError(f"{name} must be row-major or a transpose of row-major (strides {t.stride()})")
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, alpha: float = 1.0,
+         beta: float = 0.0, prec: Precision = Precision.BF16X3, stream=None) -> torch.Tensor:
+    """C <- alpha A @ B + beta C through ``la_gemm`` (eq. Matmul)."""
+    pa, m, k, lda, ta = _as_matrix(A, "A")
+    pb, k2, n, ldb, tb = _as_matrix(B, "B")
+    if k != k2:
+        raise ValueError(f"inner dimensions differ: {k} vs {k2}")
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float32, device=A.device)
+        beta = 0.0
+    pc, mc, nc, ldc, tc = _as_matrix(C, "C")
+    if (mc, nc) != (m, n) or tc:
+        raise ValueError("C must be a row-major m x n tensor")
+    ctx = context(A.device.index if A.device.index is not None else torch.cuda.current_device())
+    check(lib().la_gemm(ctx, int(ta), int(tb), m, n, k, float(alpha), pa, lda, pb, ldb,
+                        float(beta), pc, ldc, int(prec), _stream_ptr(stream)))
+    return C
+
+
+def polar_workspace_size(m: int, n: int, **opts) -> int:
+    o = make_opts(**opts)
+    return int(lib().la_polar_workspace_size(m, n, ctypes.byref(o)))
+
+
+def polar(A: torch.Tensor, *, want_h: bool = True, U: torch.Tensor | None = None,
+          H: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+          stream=None, raise_not_converged: bool = True, **opts):
+    """Polar factorisation A = U H through ``la_polar`` (Algorithm NS_Polar).
+
+    Returns (U, H or None, info dict).  ``opts`` are the fields of
+    ``la_polar_opts`` (s_minus, s0, eps, max_iter, prec_precond, prec_ns,
+    prec_h, polish, stagnation)."""
+    pa, m, n, lda, ta = _as_matrix(A, "A")
+    if ta:
+        A = A.contiguous()
+        pa, m, n, lda, ta = _as_matrix(A, "A")
+    dev = A.device
+    if U is None:
+        U = torch.empty((m, n), dtype=torch.float32, device=dev)
+    if want_h and H is None:
+        H = torch.empty((n, n), dtype=torch.float32, device=dev)
+    o = make_opts(**opts)
+    need = int(lib().la_polar_workspace_size(m, n, ctypes.byref(o)))
+    if need == 0:
+        raise LAError(Status.SHAPE, f"bad polar shape {m} x {n}")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wp = workspace.data_ptr()
+    wp_al = (wp + 255) & ~255
+    avail = workspace.numel() - (wp_al - wp)
+    pu, _, _, ldu, _ = _as_matrix(U, "U")
+    ph, ldh = (0, n)
+    if H is not None:
+        ph, _, _, ldh, _ = _as_matrix(H, "H")
+    info = PolarInfo()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    st = lib().la_polar(ctx, m, n, pa, lda, pu, ldu, ph or None, ldh, wp_al, avail,
+                        ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+    if st == Status.NOT_CONVERGED and not raise_not_converged:
+        return U, H, info.as_dict()
+    check(st)
+    return U, (H if want_h else None), info.as_dict()
+
+
+from .serve import Server  # noqa: E402

@@ -1,0 +1,253 @@
+// Auxiliary kernels of the polar driver: FP64 norm reductions (the scaling
+// ||A||_F and the step norm ||U' - U||_F of Algorithm NS_Polar, section
+// III.D), scaling, copies, symmetrisation of H, split-K reduction, and the
+// precision dispatch of the GEMM launchers.
+#include <hip/hip_runtime.h>
+
+#include "la_internal.h"
+
+namespace la {
+
+hipError_t launch_gemm_fp32(const GemmDesc &d, hipStream_t s);
+hipError_t launch_gemm_x3(const GemmDesc &d, hipStream_t s);
+hipError_t launch_gemm_x6(const GemmDesc &d, hipStream_t s);
+hipError_t launch_grouped_fp32(int, int, const GemmDesc *, const GroupItem *, int, int,
+                               hipStream_t);
+hipError_t launch_grouped_x3(int, int, const GemmDesc *, const GroupItem *, int, int,
+                             hipStream_t);
+hipError_t launch_grouped_x6(int, int, const GemmDesc *, const GroupItem *, int, int,
+                             hipStream_t);
+int tile_m_fp32();
+int tile_n_fp32();
+int tile_m_x3();
+int tile_n_x3();
+int tile_m_x6();
+int tile_n_x6();
+
+int tile_m(int prec)
+{
+    return prec == PREC_FP32 ? tile_m_fp32() : prec == PREC_BF16X3 ? tile_m_x3() : tile_m_x6();
+}
+int tile_n(int prec)
+{
+    return prec == PREC_FP32 ? tile_n_fp32() : prec == PREC_BF16X3 ? tile_n_x3() : tile_n_x6();
+}
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+void gemm_finalize(GemmDesc &d, int prec)
+{
+    d.vec_a = aligned16(d.A) && (d.lda % 4 == 0);
+    d.vec_b = aligned16(d.B) && (d.ldb % 4 == 0);
+    const int bm = tile_m(prec), bn = tile_n(prec);
+    d.tiles_m = (int)((d.M + bm - 1) / bm);
+    d.tiles_n = (int)((d.N + bn - 1) / bn);
+    if (d.gram)
+        d.num_tiles = d.tiles_n * (d.tiles_n + 1) / 2;
+    else
+        d.num_tiles = d.tiles_m * d.tiles_n;
+    if (d.M == 0 || d.N == 0)
+        d.num_tiles = 0;
+}
+
+hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: return launch_gemm_fp32(d, s);
+    case PREC_BF16X3: return launch_gemm_x3(d, s);
+    case PREC_BF16X6: return launch_gemm_x6(d, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gemm_grouped(int prec, int akc, int bkc, const GemmDesc *probs,
+                               const GroupItem *items, int num_items, int grid_size,
+                               hipStream_t s)
+{
+    switch (prec) {
+    case PREC_FP32: return launch_grouped_fp32(akc, bkc, probs, items, num_items, grid_size, s);
+    case PREC_BF16X3: return launch_grouped_x3(akc, bkc, probs, items, num_items, grid_size, s);
+    case PREC_BF16X6: return launch_grouped_x6(akc, bkc, probs, items, num_items, grid_size, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ norms
+
+namespace {
+
+constexpr int kSumsqBlocks = 1024;
+constexpr int kThreads = 256;
+
+// Block-wide FP64 sum in a fixed order: wave64 butterfly, then wave 0.
+__device__ double block_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+        sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k)
+            s += sh[k];
+    return s;
+}
+
+// Block b sums the squares of rows b, b + grid, ... ; thread t takes columns
+// t, t + 256, ...  Each square is formed and accumulated in FP64.
+__global__ void __launch_bounds__(kThreads) sumsq_kernel(const float *__restrict__ X, int64_t m,
+                                                         int64_t n, int64_t ld,
+                                                         double *__restrict__ parts)
+{
+    __shared__ double sh[kThreads / 64];
+    double acc = 0.0;
+    for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+        const float *row = X + r * ld;
+        for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+            const double x = (double)row[c];
+            acc += x * x;
+        }
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        parts[blockIdx.x] = s;
+}
+
+// One block: thread t sums parts t, t + 256, ... in order; then block_sum.
+__global__ void __launch_bounds__(kThreads) reduce_fixed_kernel(const double *__restrict__ parts,
+                                                                int64_t count,
+                                                                double *__restrict__ out)
+{
+    __shared__ double sh[kThreads / 64];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kThreads)
+        acc += parts[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        out[0] = s;
+}
+
+__global__ void scale_kernel(const float *__restrict__ X, int64_t ldx, float *__restrict__ Y,
+                             int64_t ldy, int64_t m, int64_t n, double nrm)
+{
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y)
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            Y[r * ldy + c] = (float)((double)X[r * ldx + c] / nrm);
+}
+
+__global__ void copy_kernel(const float *__restrict__ X, int64_t ldx, float *__restrict__ Y,
+                            int64_t ldy, int64_t m, int64_t n)
+{
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y)
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            Y[r * ldy + c] = X[r * ldx + c];
+}
+
+// 32 x 32 blocks on or above the diagonal; each (i < j) pair is owned by one
+// thread, so the in-place update is race free.
+__global__ void symmetrize_kernel(float *H, int64_t ldh, int64_t n)
+{
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi)
+        return;
+    const int64_t i = bi * 32 + threadIdx.y, j = bj * 32 + threadIdx.x;
+    if (i >= n || j >= n || j <= i)
+        return;
+    const float a = H[i * ldh + j], b = H[j * ldh + i];
+    const float h = 0.5f * (a + b);
+    H[i * ldh + j] = h;
+    H[j * ldh + i] = h;
+}
+
+__global__ void splitk_sym_reduce_kernel(const float *__restrict__ parts, int splits, int64_t n,
+                                         float alpha, float gamma, float *__restrict__ out,
+                                         int64_t ldo)
+{
+    const int64_t nn = n * n;
+    for (int64_t r = blockIdx.y; r < n; r += gridDim.y)
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x) {
+            float acc = 0.0f;
+            for (int s = 0; s < splits; ++s)
+                acc += parts[s * nn + r * n + c];
+            float v = alpha * acc;
+            if (r == c)
+                v = v + gamma;
+            out[r * ldo + c] = v;
+        }
+}
+
+dim3 grid2d(int64_t m, int64_t n)
+{
+    int64_t gx = (n + kThreads - 1) / kThreads;
+    if (gx > 64)
+        gx = 64;
+    int64_t gy = m < 4096 ? m : 4096;
+    if (gx < 1) gx = 1;
+    if (gy < 1) gy = 1;
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
+}  // namespace
+
+int sumsq_num_partials() { return kSumsqBlocks; }
+
+hipError_t launch_sumsq(const float *X, int64_t m, int64_t n, int64_t ld, double *partials,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(sumsq_kernel, dim3(kSumsqBlocks), dim3(kThreads), 0, s, X, m, n, ld,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_fixed(const double *parts, int64_t count, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_fixed_kernel, dim3(1), dim3(kThreads), 0, s, parts, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy, int64_t m, int64_t n,
+                        double nrm, hipStream_t s)
+{
+    if (m == 0 || n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(scale_kernel, grid2d(m, n), dim3(kThreads), 0, s, X, ldx, Y, ldy, m, n,
+                       nrm);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const float *X, int64_t ldx, float *Y, int64_t ldy, int64_t m, int64_t n,
+                       hipStream_t s)
+{
+    if (m == 0 || n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(copy_kernel, grid2d(m, n), dim3(kThreads), 0, s, X, ldx, Y, ldy, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s)
+{
+    if (n <= 1)
+        return hipSuccess;
+    const int64_t nb = (n + 31) / 32;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)nb, (unsigned)nb), dim3(32, 32), 0, s,
+                       H, ldh, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n, float alpha,
+                                    float gamma, float *out, int64_t ldo, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(splitk_sym_reduce_kernel, grid2d(n, n), dim3(kThreads), 0, s, parts,
+                       splits, n, alpha, gamma, out, ldo);
+    return hipGetLastError();
+}
+
+}  // namespace la

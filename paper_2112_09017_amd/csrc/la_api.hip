@@ -1,0 +1,579 @@
+// C ABI: context, error reporting, la_gemm and the la_polar driver.
+//
+// la_polar follows Algorithm NS_Polar (section III.D of arXiv 2112.09017):
+//   U <- A / ||A||_F                                   (FP64 norm on the GPU)
+//   k_pre steps  U <- a U (I - (4/27) a^2 U^T U)       (eqs. a_def, RogueMatrix)
+//     with k_pre from the scalar recurrence of eq. (RogueScalar) on the host
+//   Newton-Schulz U' <- U (3I - U^T U) / 2 until ||U' - U||_F <= max(M,N) eps
+//     (eq. NewtonSchulz), evaluated as U' = U + U (I - U^T U) / 2, which is the
+//     same polynomial written so the small correction is formed separately
+//   H <- (U^T A + A^T U) / 2
+// Each step is two launches: the symmetric Gram (only upper tiles, the
+// polynomial coefficients applied in its epilogue) and the product with the
+// update applied in the epilogue.  The only host synchronisation per step is
+// the 8-byte readback of ||U' - U||_F^2 for the data-dependent stop test.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "la_internal.h"
+
+struct la_context {
+    int device;
+    int num_cus;
+};
+
+namespace la {
+
+static thread_local char g_err[512];
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+static la_status dev_fail(hipError_t e, const char *where)
+{
+    set_error("%s: %s", where, hipGetErrorString(e));
+    return LA_ERR_DEVICE;
+}
+
+#define LA_HIP(call, where)                        \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess)                      \
+            return dev_fail(e_, where);            \
+    } while (0)
+
+static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
+{
+    if (!a || !b || abytes == 0 || bbytes == 0)
+        return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+static size_t extent_bytes(int64_t rows, int64_t cols, int64_t ld)
+{
+    if (rows <= 0 || cols <= 0)
+        return 0;
+    return (size_t)((rows - 1) * ld + cols) * sizeof(float);
+}
+
+static int resolve(int p, int dflt)
+{
+    return p == LA_PREC_AUTO ? dflt : p;
+}
+
+static bool valid_prec(int p)
+{
+    return p == LA_PREC_AUTO || p == LA_PREC_FP32 || p == LA_PREC_BF16X3 ||
+           p == LA_PREC_BF16X6;
+}
+
+// ------------------------------------------------------------------ polar plan
+
+la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan *out)
+{
+    la_polar_opts o;
+    memset(&o, 0, sizeof o);
+    if (opts)
+        o = *opts;
+    if (m < 1 || n < 1 || m < n) {
+        set_error("polar needs m >= n >= 1 (got m=%lld n=%lld)", (long long)m, (long long)n);
+        return LA_ERR_SHAPE;
+    }
+    if (!valid_prec(o.prec_precond) || !valid_prec(o.prec_ns) || !valid_prec(o.prec_h)) {
+        set_error("invalid la_precision in la_polar_opts");
+        return LA_ERR_INVALID_ARG;
+    }
+    PolarPlan p;
+    p.m = m;
+    p.n = n;
+    p.s_minus = o.s_minus > 0 ? o.s_minus : 0.1;
+    p.s0 = o.s0 > 0 ? o.s0 : ldexp(1.0, -23);
+    p.eps = o.eps > 0 ? o.eps : ldexp(1.0, -23);
+    p.max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    p.polish = o.polish != 0;
+    p.stagnation = o.no_stagnation == 0;
+    if (!(p.s_minus < 1.0) || !isfinite(p.s0) || !isfinite(p.eps)) {
+        set_error("la_polar_opts: need 0 < s_minus < 1 and finite s0, eps");
+        return LA_ERR_INVALID_ARG;
+    }
+    p.prec_pre = resolve(o.prec_precond, PREC_BF16X6);
+    p.prec_ns = resolve(o.prec_ns, PREC_BF16X3);
+    p.prec_h = resolve(o.prec_h, PREC_BF16X3);
+    // eq. (a_def) and the recurrence of eq. (RogueScalar): the number of
+    // preconditioning steps is fixed before any matrix work.
+    p.a = 1.5 * sqrt(3.0) - p.s_minus;
+    p.c = (4.0 / 27.0) * p.a * p.a;
+    double s = p.s0;
+    int k = 0;
+    while (s < p.s_minus && k < 1000) {
+        s = p.a * s * (1.0 - p.c * s * s);
+        ++k;
+    }
+    p.k_pre = k;
+    *out = p;
+    return LA_OK;
+}
+
+int gram_splits(int64_t m, int64_t n, int prec)
+{
+    const int64_t nb = (n + tile_n(prec) - 1) / tile_n(prec);
+    const int64_t tiles = nb * (nb + 1) / 2;
+    if (tiles >= 256)
+        return 1;
+    int64_t sp = (512 + tiles - 1) / tiles;
+    sp = std::min<int64_t>(sp, m / 2048);
+    sp = std::min<int64_t>(sp, 16);
+    return (int)std::max<int64_t>(sp, 1);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct PolarWs {
+    float *X;        // m x n, ld n: the iterate's second buffer
+    float *P;        // n x n: I - c U^T U or I - U^T U
+    float *parts;    // splits x n x n split-K Gram slices (may be null)
+    double *tiles;   // per-tile step-norm partials
+    double *sumsq;   // norm partials
+    double *scal;    // [0] ||A||_F^2, [1] ||U' - U||_F^2
+    int splits;
+};
+
+static int max_splits(const PolarPlan &p)
+{
+    return std::max(gram_splits(p.m, p.n, p.prec_pre),
+                    std::max(gram_splits(p.m, p.n, p.prec_ns),
+                             gram_splits(p.m, p.n, PREC_BF16X6)));
+}
+
+static size_t max_update_tiles(const PolarPlan &p)
+{
+    size_t t = 0;
+    for (int pr : {PREC_FP32, PREC_BF16X3, PREC_BF16X6}) {
+        const size_t tm = (size_t)((p.m + tile_m(pr) - 1) / tile_m(pr));
+        const size_t tn = (size_t)((p.n + tile_n(pr) - 1) / tile_n(pr));
+        t = std::max(t, tm * tn);
+    }
+    return t;
+}
+
+size_t polar_workspace_bytes(const PolarPlan &p)
+{
+    const int sp = max_splits(p);
+    size_t b = 0;
+    b += align256((size_t)p.m * p.n * sizeof(float));
+    b += align256((size_t)p.n * p.n * sizeof(float));
+    if (sp > 1)
+        b += align256((size_t)sp * p.n * p.n * sizeof(float));
+    b += align256(max_update_tiles(p) * sizeof(double));
+    b += align256((size_t)sumsq_num_partials() * sizeof(double));
+    b += align256(8 * sizeof(double));
+    return b;
+}
+
+static PolarWs carve(const PolarPlan &p, void *ws)
+{
+    PolarWs w;
+    char *b = (char *)ws;
+    w.splits = max_splits(p);
+    w.X = (float *)b;
+    b += align256((size_t)p.m * p.n * sizeof(float));
+    w.P = (float *)b;
+    b += align256((size_t)p.n * p.n * sizeof(float));
+    w.parts = nullptr;
+    if (w.splits > 1) {
+        w.parts = (float *)b;
+        b += align256((size_t)w.splits * p.n * p.n * sizeof(float));
+    }
+    w.tiles = (double *)b;
+    b += align256(max_update_tiles(p) * sizeof(double));
+    w.sumsq = (double *)b;
+    b += align256((size_t)sumsq_num_partials() * sizeof(double));
+    w.scal = (double *)b;
+    return w;
+}
+
+// P <- alpha X^T X + gamma I (exactly symmetric), X m x n with leading dim ldx.
+static hipError_t gram_step(int prec, const float *X, int64_t ldx, int64_t m, int64_t n,
+                            float alpha, float gamma, float *P, const PolarWs &w,
+                            hipStream_t s)
+{
+    const int splits = std::min(gram_splits(m, n, prec), w.splits);
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.a_kcontig = 0;
+    d.b_kcontig = 0;
+    d.lda = ldx;
+    d.ldb = ldx;
+    d.M = n;
+    d.N = n;
+    d.gram = 1;
+    if (splits <= 1) {
+        d.A = X;
+        d.B = X;
+        d.C = P;
+        d.ldc = n;
+        d.K = m;
+        d.alpha = alpha;
+        d.gamma = gamma;
+        gemm_finalize(d, prec);
+        return launch_gemm(prec, d, s);
+    }
+    const int64_t ks = (m + splits - 1) / splits;
+    for (int sp = 0; sp < splits; ++sp) {
+        const int64_t k0 = sp * ks;
+        const int64_t kl = std::min<int64_t>(ks, m - k0);
+        GemmDesc e = d;
+        e.A = X + k0 * ldx;
+        e.B = X + k0 * ldx;
+        e.C = w.parts + (size_t)sp * n * n;
+        e.ldc = n;
+        e.K = kl > 0 ? kl : 0;
+        e.alpha = 1.0f;
+        e.gamma = 0.0f;
+        gemm_finalize(e, prec);
+        hipError_t err = launch_gemm(prec, e, s);
+        if (err != hipSuccess)
+            return err;
+    }
+    return launch_splitk_sym_reduce(w.parts, splits, n, alpha, gamma, P, n, s);
+}
+
+// Xn <- alpha X P + beta X (partials of (Xn - X)^2 per tile if tiles != null).
+static hipError_t update_step(int prec, const float *X, int64_t ldx, const float *P, int64_t n,
+                              int64_t m, float alpha, float beta, float *Xn, int64_t ldxn,
+                              double *tiles, int *ntiles, hipStream_t s)
+{
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.A = X;
+    d.lda = ldx;
+    d.a_kcontig = 1;
+    d.B = P;
+    d.ldb = n;
+    d.b_kcontig = 0;
+    d.C = Xn;
+    d.ldc = ldxn;
+    d.M = m;
+    d.N = n;
+    d.K = n;
+    d.alpha = alpha;
+    if (beta != 0.0f) {
+        d.E = X;
+        d.lde = ldx;
+        d.beta = beta;
+    }
+    d.partials = tiles;
+    gemm_finalize(d, prec);
+    if (ntiles)
+        *ntiles = d.tiles_m * d.tiles_n;
+    return launch_gemm(prec, d, s);
+}
+
+}  // namespace la
+
+using namespace la;
+
+extern "C" {
+
+const char *la_status_string(la_status s)
+{
+    switch (s) {
+    case LA_OK: return "LA_OK";
+    case LA_ERR_INVALID_ARG: return "LA_ERR_INVALID_ARG";
+    case LA_ERR_SHAPE: return "LA_ERR_SHAPE";
+    case LA_ERR_NONFINITE: return "LA_ERR_NONFINITE";
+    case LA_ERR_NOT_CONVERGED: return "LA_ERR_NOT_CONVERGED";
+    case LA_ERR_OUT_OF_MEMORY: return "LA_ERR_OUT_OF_MEMORY";
+    case LA_ERR_DEVICE: return "LA_ERR_DEVICE";
+    case LA_ERR_QUEUE_FULL: return "LA_ERR_QUEUE_FULL";
+    case LA_ERR_TOO_LARGE: return "LA_ERR_TOO_LARGE";
+    case LA_ERR_NOT_READY: return "LA_ERR_NOT_READY";
+    case LA_ERR_UNKNOWN_REQUEST: return "LA_ERR_UNKNOWN_REQUEST";
+    }
+    return "LA_ERR_UNKNOWN_STATUS";
+}
+
+const char *la_last_error(void) { return g_err; }
+
+la_status la_create(int device, la_context **out)
+{
+    g_err[0] = 0;
+    if (!out) {
+        set_error("la_create: out is NULL");
+        return LA_ERR_INVALID_ARG;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) {
+        set_error("la_create: no HIP device (%s)", hipGetErrorString(e));
+        return LA_ERR_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        set_error("la_create: device %d out of range [0, %d)", device, count);
+        return LA_ERR_INVALID_ARG;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess)
+        return dev_fail(e, "la_create: hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error("la_create: device %d is %s; this library is built for gfx950 only", device,
+                  prop.gcnArchName);
+        return LA_ERR_DEVICE;
+    }
+    la_context *c = new (std::nothrow) la_context;
+    if (!c) {
+        set_error("la_create: out of host memory");
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return LA_OK;
+}
+
+la_status la_destroy(la_context *ctx)
+{
+    delete ctx;
+    return LA_OK;
+}
+
+la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m, int64_t n, int64_t k,
+                  float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                  float beta, float *C, int64_t ldc, la_precision prec, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!valid_prec(prec)) {
+        set_error("la_gemm: invalid precision %d", (int)prec);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (m < 0 || n < 0 || k < 0) {
+        set_error("la_gemm: negative size");
+        return LA_ERR_SHAPE;
+    }
+    const int64_t a_cols = trans_a ? m : k, a_rows = trans_a ? k : m;
+    const int64_t b_cols = trans_b ? k : n, b_rows = trans_b ? n : k;
+    if (lda < std::max<int64_t>(a_cols, 1) || ldb < std::max<int64_t>(b_cols, 1) ||
+        ldc < std::max<int64_t>(n, 1)) {
+        set_error("la_gemm: leading dimension smaller than the row length");
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx) {
+        set_error("la_gemm: ctx is NULL");
+        return LA_ERR_INVALID_ARG;
+    }
+    if (m == 0 || n == 0)
+        return LA_OK;
+    if (!C || (k > 0 && (!A || !B))) {
+        set_error("la_gemm: NULL matrix pointer");
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t cb = extent_bytes(m, n, ldc);
+    if (k > 0 && (overlaps(C, cb, A, extent_bytes(a_rows, a_cols, lda)) ||
+                  overlaps(C, cb, B, extent_bytes(b_rows, b_cols, ldb)))) {
+        set_error("la_gemm: C overlaps A or B");
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_gemm: hipSetDevice");
+    const int p = resolve(prec, PREC_BF16X3);
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.A = A;
+    d.lda = lda;
+    d.a_kcontig = trans_a ? 0 : 1;
+    d.B = B;
+    d.ldb = ldb;
+    d.b_kcontig = trans_b ? 1 : 0;
+    d.C = C;
+    d.ldc = ldc;
+    d.M = m;
+    d.N = n;
+    d.K = k;
+    d.alpha = alpha;
+    if (beta != 0.0f) {
+        d.E = C;
+        d.lde = ldc;
+        d.beta = beta;
+    }
+    gemm_finalize(d, p);
+    LA_HIP(launch_gemm(p, d, (hipStream_t)hip_stream), "la_gemm: launch");
+    return LA_OK;
+}
+
+size_t la_polar_workspace_size(int64_t m, int64_t n, const la_polar_opts *opts)
+{
+    PolarPlan p;
+    if (polar_plan(m, n, opts, &p) != LA_OK)
+        return 0;
+    return polar_workspace_bytes(p);
+}
+
+la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda, float *U,
+                   int64_t ldu, float *H, int64_t ldh, void *workspace, size_t ws_bytes,
+                   const la_polar_opts *opts, la_polar_info *info, void *hip_stream)
+{
+    g_err[0] = 0;
+    PolarPlan p;
+    la_status st = polar_plan(m, n, opts, &p);
+    if (st != LA_OK)
+        return st;
+    if (lda < n || ldu < n || (H && ldh < n)) {
+        set_error("la_polar: leading dimension smaller than n");
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx || !A || !U || !workspace) {
+        set_error("la_polar: NULL argument");
+        return LA_ERR_INVALID_ARG;
+    }
+    if (((uintptr_t)workspace & 255u) != 0) {
+        set_error("la_polar: workspace must be 256-byte aligned");
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t need = polar_workspace_bytes(p);
+    if (ws_bytes < need) {
+        set_error("la_polar: workspace %zu bytes, need %zu", ws_bytes, need);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    const size_t ab = extent_bytes(m, n, lda), ub = extent_bytes(m, n, ldu);
+    const size_t hb = H ? extent_bytes(n, n, ldh) : 0;
+    if (overlaps(U, ub, A, ab) || overlaps(U, ub, workspace, need) ||
+        (H && (overlaps(H, hb, A, ab) || overlaps(H, hb, U, ub) ||
+               overlaps(H, hb, workspace, need)))) {
+        set_error("la_polar: U / H overlap A, each other or the workspace");
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_polar: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    PolarWs w = carve(p, workspace);
+
+    la_polar_info inf;
+    memset(&inf, 0, sizeof inf);
+    inf.prec_precond = p.prec_pre;
+    inf.prec_ns = p.prec_ns;
+    inf.prec_h = p.prec_h;
+    inf.last_delta = INFINITY;
+    inf.stop_reason = 2;
+
+    // ||A||_F in FP64
+    double h2[2];
+    LA_HIP(launch_sumsq(A, m, n, lda, w.sumsq, s), "la_polar: norm");
+    LA_HIP(launch_reduce_fixed(w.sumsq, sumsq_num_partials(), w.scal, s), "la_polar: norm");
+    LA_HIP(hipMemcpyAsync(h2, w.scal, sizeof(double), hipMemcpyDeviceToHost, s),
+           "la_polar: readback");
+    LA_HIP(hipStreamSynchronize(s), "la_polar: sync");
+    const double fro = sqrt(h2[0]);
+    inf.fro_norm_a = fro;
+    if (!(fro > 0.0) || !isfinite(fro)) {
+        if (info)
+            *info = inf;
+        set_error("la_polar: ||A||_F = %g (zero or not finite)", fro);
+        return LA_ERR_NONFINITE;
+    }
+
+    // ping-pong between U (ld ldu) and the workspace copy (ld n)
+    float *buf[2] = {U, w.X};
+    int64_t ld[2] = {ldu, n};
+    int cur = 0;
+    LA_HIP(launch_scale(A, lda, buf[cur], ld[cur], m, n, fro, s), "la_polar: scale");
+
+    // preconditioning: U <- a U (I - c U^T U), c = (4/27) a^2
+    for (int i = 0; i < p.k_pre; ++i) {
+        LA_HIP(gram_step(p.prec_pre, buf[cur], ld[cur], m, n, (float)(-p.c), 1.0f, w.P, w, s),
+               "la_polar: precondition gram");
+        LA_HIP(update_step(p.prec_pre, buf[cur], ld[cur], w.P, n, m, (float)p.a, 0.0f,
+                           buf[cur ^ 1], ld[cur ^ 1], nullptr, nullptr, s),
+               "la_polar: precondition update");
+        cur ^= 1;
+        inf.iters_precond++;
+    }
+
+    // Newton-Schulz: U' = U + U (I - U^T U) / 2, delta = ||U' - U||_F
+    const double tol = (double)std::max(m, n) * p.eps;
+    double prev = INFINITY;
+    const int total = p.max_iter + (p.polish ? 1 : 0);
+    bool stopped = false;
+    for (int it = 0; it < total; ++it) {
+        const bool polishing = stopped;
+        const int prec = polishing ? PREC_BF16X6 : p.prec_ns;
+        int ntiles = 0;
+        LA_HIP(gram_step(prec, buf[cur], ld[cur], m, n, -1.0f, 1.0f, w.P, w, s),
+               "la_polar: NS gram");
+        LA_HIP(update_step(prec, buf[cur], ld[cur], w.P, n, m, 0.5f, 1.0f, buf[cur ^ 1],
+                           ld[cur ^ 1], w.tiles, &ntiles, s),
+               "la_polar: NS update");
+        LA_HIP(launch_reduce_fixed(w.tiles, ntiles, w.scal + 1, s), "la_polar: delta");
+        LA_HIP(hipMemcpyAsync(h2 + 1, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s),
+               "la_polar: readback");
+        LA_HIP(hipStreamSynchronize(s), "la_polar: sync");
+        cur ^= 1;
+        inf.iters_ns++;
+        const double delta = sqrt(h2[1]);
+        inf.last_delta = delta;
+        if (!isfinite(delta)) {
+            if (info)
+                *info = inf;
+            set_error("la_polar: step norm is not finite");
+            return LA_ERR_NONFINITE;
+        }
+        if (polishing)
+            break;
+        if (delta <= tol) {
+            inf.stop_reason = 0;
+            stopped = true;
+        } else if (p.stagnation && delta < 1e-2 * sqrt((double)n) && delta > 0.5 * prev) {
+            inf.stop_reason = 1;
+            stopped = true;
+        }
+        prev = delta;
+        if (stopped && !p.polish)
+            break;
+        if (!stopped && it + 1 >= p.max_iter)
+            break;
+    }
+    if (cur != 0)
+        LA_HIP(launch_copy(buf[cur], ld[cur], U, ldu, m, n, s), "la_polar: copy");
+
+    if (H) {
+        // H = (U^T A + A^T U) / 2
+        GemmDesc d;
+        memset(&d, 0, sizeof d);
+        d.A = U;
+        d.lda = ldu;
+        d.a_kcontig = 0;
+        d.B = A;
+        d.ldb = lda;
+        d.b_kcontig = 0;
+        d.C = H;
+        d.ldc = ldh;
+        d.M = n;
+        d.N = n;
+        d.K = m;
+        d.alpha = 1.0f;
+        gemm_finalize(d, p.prec_h);
+        LA_HIP(launch_gemm(p.prec_h, d, s), "la_polar: H");
+        LA_HIP(launch_symmetrize(H, ldh, n, s), "la_polar: symmetrize");
+    }
+    LA_HIP(hipStreamSynchronize(s), "la_polar: final sync");
+    if (info)
+        *info = inf;
+    if (!stopped) {
+        set_error("la_polar: no convergence after %d Newton-Schulz steps (delta %g)",
+                  inf.iters_ns, inf.last_delta);
+        return LA_ERR_NOT_CONVERGED;
+    }
+    return LA_OK;
+}
+
+}  // extern "C"

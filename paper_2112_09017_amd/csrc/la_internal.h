@@ -1,0 +1,103 @@
+// Internal declarations shared by the host-side translation units of the
+// library (launchers, polar driver, server).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/la.h"
+
+namespace la {
+
+// Resolved product arithmetic (la_precision without AUTO).
+enum Prec : int { PREC_FP32 = 1, PREC_BF16X3 = 2, PREC_BF16X6 = 3 };
+
+// One GEMM-shaped launch: out = alpha * op(A) op(B) + beta * E + gamma * I.
+//   op(A) (M x K): a_kcontig ? A[i * lda + k] : A[k * lda + i]
+//   op(B) (K x N): b_kcontig ? B[j * ldb + k] : B[k * ldb + j]
+//   out  (M x N): C[i * ldc + j]
+//   E: optional addend (may equal C for beta * C), E[i * lde + j]
+//   gram: output is symmetric (M == N): only tiles on or above the diagonal
+//         are computed; element (i, j), i <= j, is written to (i, j) and
+//         (j, i), so the result is exactly symmetric.
+//   partials: optional, one FP64 per output tile: sum over the tile of
+//         (out - E)^2, for the step norm ||X' - X||_F; requires E.
+struct GemmDesc {
+    const float *A;
+    const float *B;
+    float *C;
+    const float *E;
+    double *partials;
+    int64_t lda, ldb, ldc, lde;
+    int64_t M, N, K;
+    float alpha, beta, gamma;
+    int a_kcontig, b_kcontig;
+    int gram;
+    int vec_a, vec_b;  // operand addresses allow 16-byte vector loads
+    int tiles_m, tiles_n;
+    int num_tiles;     // tiles launched (upper triangle only for gram)
+};
+
+// Tile geometry of each precision (fixed, so results never depend on what
+// else is in a launch).
+int tile_m(int prec);
+int tile_n(int prec);
+
+// Fills the derived fields (vec flags, tile counts) of d.
+void gemm_finalize(GemmDesc &d, int prec);
+
+hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s);
+
+// Grouped launch: every item is one output tile of one problem; all problems
+// share precision and operand layouts.  probs / items live in device memory.
+struct GroupItem {
+    int prob;
+    int tile;   // linear tile index within the problem
+};
+hipError_t launch_gemm_grouped(int prec, int a_kcontig, int b_kcontig,
+                               const GemmDesc *probs_dev,
+                               const GroupItem *items_dev, int num_items,
+                               int grid_size, hipStream_t s);
+
+// Auxiliary kernels (aux_kernels.hip).
+// Sum of squares of an m x n strided matrix into nparts FP64 partials.
+int sumsq_num_partials();
+hipError_t launch_sumsq(const float *X, int64_t m, int64_t n, int64_t ld,
+                        double *partials, hipStream_t s);
+// out[0] = sum of parts[0..count) in a fixed order (deterministic).
+hipError_t launch_reduce_fixed(const double *parts, int64_t count, double *out,
+                               hipStream_t s);
+// Y = X / nrm, element-wise in FP64 then rounded to FP32 (so scaling A by a
+// power of two leaves Y bitwise unchanged).
+hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy,
+                        int64_t m, int64_t n, double nrm, hipStream_t s);
+// Y = X (strided copy).
+hipError_t launch_copy(const float *X, int64_t ldx, float *Y, int64_t ldy,
+                       int64_t m, int64_t n, hipStream_t s);
+// In place H <- (H + H^T) / 2 for an n x n matrix.
+hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s);
+// Split-K reduction for a symmetric (gram) output: out(i, j) =
+// alpha * sum_s part_s(i, j) + gamma * [i == j], summed over s in order;
+// parts are `splits` exactly symmetric n x n slices (row-major, ld n).
+hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n,
+                                    float alpha, float gamma, float *out,
+                                    int64_t ldo, hipStream_t s);
+
+// Polar building blocks shared by la_polar and the server.
+struct PolarPlan {
+    int64_t m, n;
+    double s_minus, s0, eps, a, c;
+    int k_pre, max_iter, polish, stagnation;
+    int prec_pre, prec_ns, prec_h;
+};
+la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts,
+                     PolarPlan *out);
+// Number of split-K slices the Gram of an m x n iterate uses.
+int gram_splits(int64_t m, int64_t n, int prec);
+size_t polar_workspace_bytes(const PolarPlan &p);
+
+// Thread-local error text.
+void set_error(const char *fmt, ...);
+
+}  // namespace la

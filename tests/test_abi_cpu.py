@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every symbol include/la.h declares, and
+rejects bad arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "la.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(la_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2112_09017_amd import _binding
+    return _binding.lib()
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    for n in ("la_create", "la_destroy", "la_gemm", "la_polar", "la_polar_workspace_size",
+              "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
+              "la_status_string", "la_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    from paper_2112_09017_amd import _binding
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert name in _binding.SIGNATURES, f"binding lacks {name}"
+
+
+def test_library_is_built_for_gfx950():
+    from paper_2112_09017_amd import _binding
+    blob = open(_binding.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+def test_status_strings(L):
+    assert L.la_status_string(0) == b"LA_OK"
+    assert L.la_status_string(4) == b"LA_ERR_NOT_CONVERGED"
+    assert L.la_status_string(999) == b"LA_ERR_UNKNOWN_STATUS"
+
+
+def test_gemm_argument_validation_without_device(L):
+    # bad precision, negative size, short leading dimension, then NULL context
+    assert L.la_gemm(None, 0, 0, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 7, None) == 1
+    assert L.la_last_error().startswith(b"la_gemm: invalid precision")
+    assert L.la_gemm(None, 0, 0, -1, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0, None) == 2
+    assert L.la_gemm(None, 0, 0, 4, 4, 8, 1.0, None, 4, None, 4, 0.0, None, 4, 0, None) == 2
+    assert L.la_gemm(None, 1, 0, 8, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0, None) == 2
+    assert L.la_gemm(None, 0, 0, 4, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0, None) == 1
+    assert b"ctx is NULL" in L.la_last_error()
+
+
+def test_polar_argument_validation_without_device(L):
+    from paper_2112_09017_amd import _binding
+    assert L.la_polar_workspace_size(3, 5, None) == 0          # M < N
+    assert L.la_polar_workspace_size(0, 0, None) == 0
+    ws = L.la_polar_workspace_size(300, 200, None)
+    assert ws >= 4 * (300 * 200 + 200 * 200)
+    o = _binding.make_opts(prec_ns=9)
+    assert L.la_polar_workspace_size(8, 8, ctypes.byref(o)) == 0
+    assert L.la_polar(None, 3, 5, None, 5, None, 5, None, 5, None, 0, None, None, None) == 2
+    assert L.la_polar(None, 8, 8, None, 4, None, 8, None, 8, None, 0, None, None, None) == 2
+    assert L.la_polar(None, 8, 8, None, 8, None, 8, None, 8, None, 0, None, None, None) == 1
+
+
+def test_create_reports_missing_device(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = ctypes.c_void_p()
+    st = L.la_create(0, ctypes.byref(out))
+    assert st == 6 and not out.value
+    assert L.la_last_error()
+
+
+def test_destroy_accepts_null(L):
+    assert L.la_destroy(None) == 0
+    assert L.la_serve_destroy(None) == 0

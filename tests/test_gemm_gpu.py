@@ -1,0 +1,180 @@
+"""la_gemm on the GPU against the FP64 oracle (eq. Matmul).
+
+Tolerance: normwise ||C - C64||_F / (||A||_F ||B||_F) <= 1e-6 on every path
+for the workload sizes (K >= 256).  BF16X3 represents each operand as hi + lo
+with relative error up to 2^-16 and drops lo*lo, so its normwise error on
+i.i.d. data is about 2^-16 / sqrt(K); below K = 256 that exceeds 1e-6, and the
+bound used there is max(1e-6, 2^-16 / sqrt(K)).  Integer-valued inputs whose
+sums stay below 2^24 are exact on every path, so those compare bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import la_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def tol(prec, k):
+    if prec == "BF16X3":
+        return max(TOL, 2.0 ** -16 / np.sqrt(max(k, 1)))
+    return TOL
+
+
+@pytest.fixture(scope="module")
+def la():
+    import paper_2112_09017_amd as la
+    la.lib()
+    return la
+
+
+PRECS = ["FP32", "BF16X3", "BF16X6"]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def gpu_gemm(la, A, B, prec, ta=False, tb=False, C0=None, alpha=1.0, beta=0.0):
+    """A, B are the logical op(A), op(B); ta/tb store them transposed."""
+    Ad = dev(A.T).T if ta else dev(A)
+    Bd = dev(B.T).T if tb else dev(B)
+    Cd = dev(C0) if C0 is not None else None
+    out = la.gemm(Ad, Bd, Cd, alpha=alpha, beta=beta, prec=getattr(la.Precision, prec))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def normwise(C, ref, A, B):
+    return np.linalg.norm(C.astype(np.float64) - ref) / (np.linalg.norm(A) * np.linalg.norm(B))
+
+
+SHAPES = [(1, 1, 1), (32, 32, 16), (256, 256, 256), (37, 53, 29), (300, 270, 513),
+          (520, 1030, 33), (257, 64, 1000), (96, 700, 7)]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_gaussian_normwise(la, prec, shape):
+    m, n, k = shape
+    A = la_inputs.gaussian((m, k), 1000 + m)
+    B = la_inputs.gaussian((k, n), 2000 + n)
+    C = gpu_gemm(la, A, B, prec)
+    err = normwise(C, oracle.gemm(A, B), A, B)
+    print(f"{prec} {shape} normwise {err:.3e}")
+    assert err <= tol(prec, k)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_integer_exact_all_layouts(la, prec, ta, tb):
+    m, n, k = 290, 333, 517
+    A = la_inputs.integer_matrix((m, k), 5)
+    B = la_inputs.integer_matrix((k, n), 6)
+    C = gpu_gemm(la, A, B, prec, bool(ta), bool(tb))
+    ref = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    assert np.array_equal(C, ref)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_alpha_beta_and_k_zero(la, prec):
+    m, n, k = 130, 250, 70
+    A = la_inputs.integer_matrix((m, k), 7)
+    B = la_inputs.integer_matrix((k, n), 8)
+    C0 = la_inputs.integer_matrix((m, n), 9)
+    C = gpu_gemm(la, A, B, prec, C0=C0, alpha=2.0, beta=-3.0)
+    ref = 2 * (A.astype(np.int64) @ B.astype(np.int64)) - 3 * C0.astype(np.int64)
+    assert np.array_equal(C, ref.astype(np.float32))
+    # k = 0: C <- beta C
+    Ad = torch.zeros((m, 0), device="cuda")
+    Bd = torch.zeros((0, n), device="cuda")
+    Cd = dev(C0)
+    la.gemm(Ad, Bd, Cd, beta=0.5, prec=getattr(la.Precision, prec))
+    torch.cuda.synchronize()
+    assert np.array_equal(Cd.cpu().numpy(), 0.5 * C0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_beta_zero_does_not_read_c(la, prec):
+    A = la_inputs.gaussian((64, 48), 10)
+    B = la_inputs.gaussian((48, 80), 11)
+    Cd = torch.full((64, 80), float("nan"), device="cuda")
+    la.gemm(dev(A), dev(B), Cd, beta=0.0, prec=getattr(la.Precision, prec))
+    torch.cuda.synchronize()
+    assert np.isfinite(Cd.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_identity_and_permutation(la, prec):
+    """FP32 and BF16X6 carry all 24 significant bits of each operand, so
+    A I and A P are exact; BF16X3 keeps about 17 bits (hi + lo)."""
+    n = 300
+    A = la_inputs.gaussian((200, n), 12)
+    eye = np.eye(n, dtype=np.float32)
+    perm = np.random.default_rng(13).permutation(n)
+    Pm = np.eye(n, dtype=np.float32)[:, perm]
+    CI = gpu_gemm(la, A, eye, prec)
+    CP = gpu_gemm(la, A, Pm, prec)
+    if prec == "BF16X3":
+        assert np.abs(CI - A).max() <= 2.0 ** -16 * np.abs(A).max()
+        assert np.array_equal(CP, CI[:, perm])
+    else:
+        assert np.array_equal(CI, A)
+        assert np.array_equal(CP, A[:, perm])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_padded_and_unaligned_operands(la, prec):
+    """Leading dimensions larger than the row and 4-byte-offset bases take the
+    guarded scalar load path; results must not change."""
+    m, n, k = 150, 170, 190
+    A = la_inputs.gaussian((m, k), 14)
+    B = la_inputs.gaussian((k, n), 15)
+    bigA = torch.zeros((m, k + 9), device="cuda")
+    bigA[:, 1:k + 1] = dev(A)
+    bigB = torch.zeros((k, n + 3), device="cuda")
+    bigB[:, :n] = dev(B)
+    C = torch.empty((m, n + 5), device="cuda")[:, :n]
+    la.gemm(bigA[:, 1:k + 1], bigB[:, :n], C, prec=getattr(la.Precision, prec))
+    torch.cuda.synchronize()
+    ref_gpu = gpu_gemm(la, A, B, prec)
+    assert np.array_equal(C.cpu().numpy(), ref_gpu)
+    assert normwise(ref_gpu, oracle.gemm(A, B), A, B) <= TOL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_nonfinite_inputs_stay_local(la, prec):
+    A = la_inputs.gaussian((70, 90), 16)
+    B = la_inputs.gaussian((90, 60), 17)
+    A[5, 7] = np.inf
+    B[3, 11] = np.nan
+    C = gpu_gemm(la, A, B, prec)
+    bad_rows = np.zeros(70, bool); bad_rows[5] = True
+    bad_cols = np.zeros(60, bool); bad_cols[11] = True
+    assert not np.isfinite(C[5, :]).any()
+    assert not np.isfinite(C[:, 11]).any()
+    assert np.isfinite(C[~bad_rows][:, ~bad_cols]).all()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_deterministic(la, prec):
+    A = la_inputs.gaussian((600, 700), 18)
+    B = la_inputs.gaussian((700, 500), 19)
+    C1 = gpu_gemm(la, A, B, prec)
+    C2 = gpu_gemm(la, A, B, prec)
+    assert np.array_equal(C1, C2)
+
+
+def test_precision_ordering(la):
+    """FP32 and BF16X6 are FP32-level; BF16X3 is within the tolerance but less
+    accurate (about 2^-17 per operand split) -- the expected ordering."""
+    A = la_inputs.gaussian((512, 2048), 20)
+    B = la_inputs.gaussian((2048, 512), 21)
+    ref = oracle.gemm(A, B)
+    e = {p: normwise(gpu_gemm(la, A, B, p), ref, A, B) for p in PRECS}
+    print(e)
+    assert e["BF16X6"] < e["BF16X3"] and e["FP32"] < e["BF16X3"]
+    assert max(e.values()) <= TOL
