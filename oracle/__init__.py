@@ -74,6 +74,8 @@ def _bind(path: str):
     lib.orc_polar.restype = ctypes.c_int
     lib.orc_polar_2x2.argtypes = [dp, dp, dp]
     lib.orc_polar_2x2.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
     return lib
 
 
@@ -171,6 +173,10 @@ class Oracle:
                        _REASONS.get(info.stop_reason, "?"))
         return U, H, pi
 
+    def num_threads(self) -> int:
+        """OpenMP threads the oracle's GEMM uses."""
+        return int(self._lib.orc_num_threads())
+
     def polar_2x2(self, A):
         """Closed-form polar factors (U, H) of a full-rank 2 x 2 matrix."""
         A = _f64(A).reshape(2, 2)
@@ -211,6 +217,10 @@ def polar(*a, **k):
 
 def polar_2x2(*a, **k):
     return _load().polar_2x2(*a, **k)
+
+
+def num_threads():
+    return _load().num_threads()
 
 
 gemm.__doc__ = Oracle.gemm.__doc__

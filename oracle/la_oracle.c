@@ -15,6 +15,7 @@
  * conjugate transposes; for real data they are plain transposes.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -69,6 +70,9 @@ int orc_gemm(int trans_a, int trans_b, int64_t m, int64_t n, int64_t k,
     free(bc);
     return 0;
 }
+
+/* Threads the OpenMP loops use (for reporting CPU-baseline core counts). */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* Frobenius norm, ||A||_F = sqrt(tr(A A^T)) (section III.D). */
 double orc_fro(int64_t m, int64_t n, const double *A, int64_t lda)
