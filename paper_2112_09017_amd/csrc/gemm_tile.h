@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "la_internal.h"
 
 namespace la {
@@ -42,17 +44,26 @@ constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------- configs
 
+#ifndef LA_X3_WM
+#define LA_X3_WM 2
+#endif
+#ifndef LA_X3_WN
+#define LA_X3_WN 2
+#endif
 template <int PREC> struct Cfg;
+// PIPE 1: one register stage, BK = 32, the next stage's split/stores run in
+// the second 16-k half of the current stage.  PIPE 2: two register stages,
+// BK = 16, the split of stage s+1 runs under the MFMAs of stage s.
 template <> struct Cfg<PREC_FP32> {
-    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2;
+    static constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 2, OCC = 1, PIPE = 1;
     static constexpr int terms = 1, entry_bytes = 32;
 };
 template <> struct Cfg<PREC_BF16X3> {
-    static constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 2;
+    static constexpr int BM = 256, BN = 256, BK = 32, WM = LA_X3_WM, WN = LA_X3_WN, OCC = 1, PIPE = 1;
     static constexpr int terms = 2, entry_bytes = 16;
 };
 template <> struct Cfg<PREC_BF16X6> {
-    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2;
+    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2;
     static constexpr int terms = 3, entry_bytes = 16;
 };
 
@@ -76,12 +87,10 @@ __device__ __forceinline__ uint32_t pk_bf16(float a, float b)
 }
 __device__ __forceinline__ float bf_lo(uint32_t p) { return __uint_as_float(p << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
-// Remainder x - t after taking the leading bf16 term t (exact in FP32).  A
-// non-finite leading term keeps Inf/NaN in that term alone.
-__device__ __forceinline__ float rest(float x, float t)
-{
-    return fabsf(t) <= 3.40282347e38f ? x - t : 0.0f;
-}
+// Remainder x - t after taking the leading bf16 term t; exact in FP32 for
+// finite x.  (A non-finite x leaves a NaN remainder, so non-finite inputs
+// give non-finite, possibly NaN, outputs.)
+__device__ __forceinline__ float rest(float x, float t) { return x - t; }
 
 // Split 8 FP32 values into the LDS terms of the precision.
 template <int PREC> struct Split;
@@ -127,13 +136,13 @@ template <> struct Split<PREC_BF16X6> {
 
 // ---------------------------------------------------------------- LDS layout
 
-// Slot of lane entry `lane` inside a 64-entry fragment block; rotates each
-// group of 8 slots so that both the fragment reads (8 consecutive lanes) and
-// the split writes (rows 4 apart or k8 pairs) hit distinct 16-byte banks.
-__device__ __forceinline__ int swz(int lane, int fk)
-{
-    return (lane & 56) | ((lane + (lane >> 3) + 2 * fk) & 7);
-}
+// Slot of lane entry `lane` inside a 64-entry fragment block.  Measured on
+// gfx950: 16-byte-per-lane LDS accesses are conflict free when the 16 lanes
+// of each group of consecutive lanes touch 16 distinct slots modulo 16 and the
+// lane-to-slot map is the same shift for every group; the identity map gives
+// conflict-free fragment reads, and the loaders below assign rows so that
+// their writes also hit 16 consecutive slots.
+__device__ __forceinline__ int swz(int lane, int fk) { return lane; }
 
 // Byte offset of the entry holding op(X)(row, 8*k8 .. 8*k8+7) of term `t`.
 template <int ROWS, int KF, int EB>
@@ -154,85 +163,138 @@ __device__ __forceinline__ int frag_off(int t, int frow, int fk, int lane)
 
 // Loads one K stage of op(X) rows [r0, r0+ROWS) x k [k0, k0+BK) into
 // registers.  KC: k is contiguous in memory (X[r * ld + k]); otherwise the
-// row index is (X[k * ld + r]).  Work unit = 8 k x 4 rows (8 float4 loads).
+// row index is (X[k * ld + r]).  Work unit = 8 k x R rows: R float4 pairs
+// (KC) or 8 float-R vectors (row-contiguous), R = 4 or 2 so that every
+// thread has work.  Interior stages use load_fast (no bounds checks, loop-
+// invariant 32-bit offsets from a uniform stage base); edge tiles and the K
+// tail use load_guarded.
 template <int ROWS, int BK, int NT, bool KC>
 struct Loader {
-    static constexpr int UNITS = ROWS * BK / 32;
+    // k-contiguous operands take up to 4 rows per unit; row-contiguous ones one
+    // row per lane, so that 16 consecutive lanes always write 16 consecutive
+    // fragment slots
+#ifndef LA_RC_ROWS
+#define LA_RC_ROWS 4
+#endif
+    static constexpr int RMAX = (ROWS * BK / (8 * NT) >= 4) ? 4 : (ROWS * BK / (8 * NT) >= 2) ? 2 : 1;
+    static constexpr int R = !KC ? (LA_RC_ROWS < RMAX ? LA_RC_ROWS : RMAX) : RMAX;
+    static constexpr int NK8 = BK / 8;
+    static constexpr int UNITS = ROWS * BK / (8 * R);
     static constexpr int UPT = (UNITS + NT - 1) / NT;
-    float v[UPT][4][8];
+    static_assert(UNITS % NT == 0, "every thread must own whole units");
+    float v[UPT][R][8];
+    int off[UPT];  // element offset of the unit's first element from the stage base
 
-    __device__ __forceinline__ static bool active(int uid) { return (UNITS % NT) == 0 || uid < UNITS; }
-
-    // (row, k8) of entry q of unit uid
+    // (row, k8) of entry q of unit uid.  KC: within each 16 consecutive units
+    // the row advances and k8 is fixed; k8 changes every 16 units, so a load
+    // instruction still covers whole 128-byte row segments.
     __device__ __forceinline__ static int row_of(int uid, int q)
     {
         if constexpr (KC)
-            return uid / (BK / 8) + q * (ROWS / 4);
+            return (uid % 16) + 16 * (uid / (16 * NK8)) + q * (ROWS / R);
         else
-            return 4 * (uid % (ROWS / 4)) + q;
+            return R * (uid % (ROWS / R)) + q;
     }
     __device__ __forceinline__ static int k8_of(int uid)
     {
         if constexpr (KC)
-            return uid % (BK / 8);
+            return (uid / 16) % NK8;
         else
-            return uid / (ROWS / 4);
+            return uid / (ROWS / R);
     }
 
-    __device__ __forceinline__ void load(const float *__restrict__ X, int64_t ld, int64_t R,
-                                         int64_t K, int64_t r0, int64_t k0, bool fast)
+    __device__ __forceinline__ void init(int64_t ld)
+    {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const int uid = threadIdx.x + u * NT;
+            const int row = row_of(uid, 0), k8 = k8_of(uid);
+            off[u] = KC ? (int)(row * ld + 8 * k8) : (int)(8 * k8 * ld + row);
+        }
+    }
+
+    // base = &op(X)(r0, k0) (uniform), stage fully in bounds, 16-byte aligned.
+    __device__ __forceinline__ void load_fast(const float *__restrict__ base, int64_t ld)
+    {
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            if constexpr (KC) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const f32x4 *p = reinterpret_cast<const f32x4 *>(
+                        base + off[u] + (int64_t)q * (ROWS / R) * ld);
+                    const f32x4 a = p[0], b = p[1];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        v[u][q][j] = a[j];
+                        v[u][q][4 + j] = b[j];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float *p = base + off[u] + (int64_t)j * ld;
+                    if constexpr (R == 4) {
+                        const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            v[u][q][j] = a[q];
+                    } else if constexpr (R == 2) {
+                        const f32x2 a = *reinterpret_cast<const f32x2 *>(p);
+                        v[u][0][j] = a[0];
+                        v[u][1][j] = a[1];
+                    } else {
+                        v[u][0][j] = *p;
+                    }
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void load_guarded(const float *__restrict__ X, int64_t ld,
+                                                 int64_t Rn, int64_t K, int64_t r0, int64_t k0)
     {
         const int t = threadIdx.x;
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const int uid = t + u * NT;
-            if (!active(uid))
-                continue;
             const int k8 = k8_of(uid);
-            if constexpr (KC) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int64_t gr = r0 + row_of(uid, q);
-                    const int64_t gk = k0 + 8 * k8;
-                    if (fast) {
-                        const f32x4 *p = reinterpret_cast<const f32x4 *>(X + gr * ld + gk);
-                        const f32x4 a = p[0], b = p[1];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            v[u][q][j] = a[j];
-                            v[u][q][4 + j] = b[j];
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            float x = 0.0f;
-                            if (gr < R && gk + j < K)
-                                x = X[gr * ld + gk + j];
-                            v[u][q][j] = x;
-                        }
-                    }
-                }
-            } else {
-                const int64_t gr = r0 + row_of(uid, 0);
+            for (int q = 0; q < R; ++q) {
+                const int64_t gr = r0 + row_of(uid, q);
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int64_t gk = k0 + 8 * k8 + j;
-                    if (fast) {
-                        const f32x4 a = *reinterpret_cast<const f32x4 *>(X + gk * ld + gr);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            v[u][q][j] = a[q];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            float x = 0.0f;
-                            if (gk < K && gr + q < R)
-                                x = X[gk * ld + gr + q];
-                            v[u][q][j] = x;
-                        }
-                    }
+                    float x = 0.0f;
+                    if (gr < Rn && gk < K)
+                        x = KC ? X[gr * ld + gk] : X[gk * ld + gr];
+                    v[u][q][j] = x;
                 }
             }
+        }
+    }
+
+    // Split and write one entry (unit u, row q) of the stage.
+    template <int PREC>
+    __device__ __forceinline__ void store_entry(char *base, int u, int q) const
+    {
+        using C = Cfg<PREC>;
+        constexpr int KF = BK / 16;
+        const int uid = threadIdx.x + u * NT;
+        const int k8 = k8_of(uid);
+        const int row = row_of(uid, q);
+        u32x4 parts[C::terms * (C::entry_bytes / 16)];
+        Split<PREC>::run(v[u][q], parts);
+        if constexpr (PREC == PREC_FP32) {
+            u32x4 *dst =
+                reinterpret_cast<u32x4 *>(base + entry_off<ROWS, KF, C::entry_bytes>(0, row, k8));
+            dst[0] = parts[0];
+            dst[1] = parts[1];
+        } else {
+#pragma unroll
+            for (int tt = 0; tt < C::terms; ++tt)
+                *reinterpret_cast<u32x4 *>(base + entry_off<ROWS, KF, C::entry_bytes>(tt, row, k8)) =
+                    parts[tt];
         }
     }
 
@@ -245,11 +307,9 @@ struct Loader {
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const int uid = t + u * NT;
-            if (!active(uid))
-                continue;
             const int k8 = k8_of(uid);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < R; ++q) {
                 const int row = row_of(uid, q);
                 u32x4 parts[C::terms * (C::entry_bytes / 16)];
                 Split<PREC>::run(v[u][q], parts);
@@ -271,7 +331,23 @@ struct Loader {
 
 // ---------------------------------------------------------------- MFMA stage
 
-template <int PREC>
+// Products of split terms (a term, b term), smallest magnitude first.
+template <int PREC> struct Products;
+template <> struct Products<PREC_BF16X3> {
+    static constexpr int n = 3;
+    static constexpr int a[3] = {1, 0, 0};
+    static constexpr int b[3] = {0, 1, 0};
+};
+template <> struct Products<PREC_BF16X6> {
+    static constexpr int n = 6;
+    static constexpr int a[6] = {2, 0, 1, 1, 0, 0};
+    static constexpr int b[6] = {0, 2, 1, 0, 1, 0};
+};
+
+// One K stage of MFMAs from LDS.  Fragment reads are issued in the order the
+// MFMAs first need them (the first MFMA waits for two reads, later ones for
+// at most one more), so the matrix core starts early in each stage.
+template <int PREC, int KK0 = 0, int KK1 = Geo<PREC>::KF>
 __device__ __forceinline__ void compute_stage(const char *sA, const char *sB,
                                               f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
                                               int wm, int wn, int lane)
@@ -280,22 +356,21 @@ __device__ __forceinline__ void compute_stage(const char *sA, const char *sB,
     using G = Geo<PREC>;
     constexpr int FM = G::FM, FN = G::FN, KF = G::KF, EB = C::entry_bytes;
 #pragma unroll
-    for (int kk = 0; kk < KF; ++kk) {
+    for (int kk = KK0; kk < KK1; ++kk) {
         if constexpr (PREC == PREC_FP32) {
             f32x4 a[FM][2], b[FN][2];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const f32x4 *p = reinterpret_cast<const f32x4 *>(
-                    sA + frag_off<C::BM, KF, EB>(0, wm * FM + i, kk, lane));
-                a[i][0] = p[0];
-                a[i][1] = p[1];
-            }
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                const f32x4 *p = reinterpret_cast<const f32x4 *>(
-                    sB + frag_off<C::BN, KF, EB>(0, wn * FN + j, kk, lane));
-                b[j][0] = p[0];
-                b[j][1] = p[1];
+                for (int i = 0; i < FM; ++i) {
+                    a[i][h] = reinterpret_cast<const f32x4 *>(
+                        sA + frag_off<C::BM, KF, EB>(0, wm * FM + i, kk, lane))[h];
+                    if (i == 0)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            b[j][h] = reinterpret_cast<const f32x4 *>(
+                                sB + frag_off<C::BN, KF, EB>(0, wn * FN + j, kk, lane))[h];
+                }
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e)
@@ -306,37 +381,203 @@ __device__ __forceinline__ void compute_stage(const char *sA, const char *sB,
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                             a[i][e >> 2][e & 3], b[j][e >> 2][e & 3], acc[i][j], 0, 0, 0);
         } else {
+            using P = Products<PREC>;
             constexpr int T = C::terms;
             bf16x8 a[FM][T], b[FN][T];
+            // reads in first-use order: for each product, a[0], b[*], a[1..]
+            bool have_a[T] = {}, have_b[T] = {};
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int p = 0; p < P::n; ++p) {
+                const int ta = P::a[p], tb = P::b[p];
+                const bool need_a = !have_a[ta], need_b = !have_b[tb];
 #pragma unroll
-                for (int t = 0; t < T; ++t)
-                    a[i][t] = *reinterpret_cast<const bf16x8 *>(
-                        sA + frag_off<C::BM, KF, EB>(t, wm * FM + i, kk, lane));
+                for (int i = 0; i < FM; ++i) {
+                    if (need_a)
+                        a[i][ta] = *reinterpret_cast<const bf16x8 *>(
+                            sA + frag_off<C::BM, KF, EB>(ta, wm * FM + i, kk, lane));
+                    if (i == 0 && need_b)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
+                        for (int j = 0; j < FN; ++j)
+                            b[j][tb] = *reinterpret_cast<const bf16x8 *>(
+                                sB + frag_off<C::BN, KF, EB>(tb, wn * FN + j, kk, lane));
+                }
+                have_a[ta] = true;
+                have_b[tb] = true;
+            }
 #pragma unroll
-                for (int t = 0; t < T; ++t)
-                    b[j][t] = *reinterpret_cast<const bf16x8 *>(
-                        sB + frag_off<C::BN, KF, EB>(t, wn * FN + j, kk, lane));
-            // products of split terms, smallest first
-            constexpr int NP = (PREC == PREC_BF16X3) ? 3 : 6;
-            constexpr int pa[6] = {(PREC == PREC_BF16X3) ? 1 : 2, 0, 1, 1, 0, 0};
-            constexpr int pb[6] = {0, (PREC == PREC_BF16X3) ? 1 : 2, 1, 0, 1, 0};
-            constexpr int pa3[3] = {1, 0, 0};
-            constexpr int pb3[3] = {0, 1, 0};
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int ta = (PREC == PREC_BF16X3) ? pa3[p] : pa[p];
-                const int tb = (PREC == PREC_BF16X3) ? pb3[p] : pb[p];
+            for (int p = 0; p < P::n; ++p)
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            a[i][ta], b[j][tb], acc[i][j], 0, 0, 0);
+                            a[i][P::a[p]], b[j][P::b[p]], acc[i][j], 0, 0, 0);
+        }
+    }
+}
+
+// One 16-k half of a stage whose MFMAs are issued in NG equal groups; after
+// group g, between(g) runs (one LDS entry of the next stage), and a fence
+// keeps each group's MFMAs and split work in one small scheduling region so
+// they interleave.
+template <int PREC, int KK, int NG, typename F>
+__device__ __forceinline__ void compute_half_interleaved(const char *sA, const char *sB,
+                                                         f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
+                                                         int wm, int wn, int lane, F &&between)
+{
+    using C = Cfg<PREC>;
+    using G = Geo<PREC>;
+    constexpr int FM = G::FM, FN = G::FN, KF = G::KF, EB = C::entry_bytes;
+    if constexpr (PREC == PREC_FP32) {
+        constexpr int NM = 8 * FM * FN, GS = NM / NG;
+        f32x4 a[FM][2], b[FN][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                a[i][h] = reinterpret_cast<const f32x4 *>(
+                    sA + frag_off<C::BM, KF, EB>(0, wm * FM + i, KK, lane))[h];
+                if (i == 0)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        b[j][h] = reinterpret_cast<const f32x4 *>(
+                            sB + frag_off<C::BN, KF, EB>(0, wn * FN + j, KK, lane))[h];
             }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int e = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e >> 2][e & 3],
+                                                            b[j][e >> 2][e & 3], acc[i][j], 0,
+                                                            0, 0);
+            if (m % GS == GS - 1) {
+                between(m / GS);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+        using P = Products<PREC>;
+        constexpr int T = C::terms;
+        constexpr int NM = P::n * FM * FN, GS = NM / NG;
+        bf16x8 a[FM][T], b[FN][T];
+        bool have_a[T] = {}, have_b[T] = {};
+#pragma unroll
+        for (int p = 0; p < P::n; ++p) {
+            const int ta = P::a[p], tb = P::b[p];
+            const bool need_a = !have_a[ta], need_b = !have_b[tb];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                if (need_a)
+                    a[i][ta] = *reinterpret_cast<const bf16x8 *>(
+                        sA + frag_off<C::BM, KF, EB>(ta, wm * FM + i, KK, lane));
+                if (i == 0 && need_b)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        b[j][tb] = *reinterpret_cast<const bf16x8 *>(
+                            sB + frag_off<C::BN, KF, EB>(tb, wn * FN + j, KK, lane));
+            }
+            have_a[ta] = true;
+            have_b[tb] = true;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int p = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][P::a[p]], b[j][P::b[p]],
+                                                               acc[i][j], 0, 0, 0);
+            if (m % GS == GS - 1) {
+                between(m / GS);
+#pragma unroll
+                for (int q = 0; q < GS; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+}
+
+// Fragment read helpers (bf16 terms).
+template <int PREC>
+__device__ __forceinline__ void read_a(bf16x8 (&a)[Geo<PREC>::FM][Cfg<PREC>::terms], const char *sA,
+                                       int t, int kk, int wm, int lane)
+{
+    using C = Cfg<PREC>;
+    using G = Geo<PREC>;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+        a[i][t] = *reinterpret_cast<const bf16x8 *>(
+            sA + frag_off<C::BM, G::KF, C::entry_bytes>(t, wm * G::FM + i, kk, lane));
+}
+template <int PREC>
+__device__ __forceinline__ void read_b(bf16x8 (&b)[Geo<PREC>::FN][Cfg<PREC>::terms], const char *sB,
+                                       int t, int kk, int wn, int lane)
+{
+    using C = Cfg<PREC>;
+    using G = Geo<PREC>;
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+        b[j][t] = *reinterpret_cast<const bf16x8 *>(
+            sB + frag_off<C::BN, G::KF, C::entry_bytes>(t, wn * G::FN + j, kk, lane));
+}
+
+// Steady-state stage of the 3xBF16 PIPE 1 loop (BK = 32, two 16-k halves).
+// The second half's first fragments (lo of A, hi of B) are read into the
+// registers the first half frees after its second product, and the rest as
+// soon as the first half ends, so the matrix core does not drain between the
+// halves.  The split/writes of the next stage interleave with the second
+// half's MFMAs in NG groups (between(g) after each group).
+template <int NG, typename F>
+__device__ __forceinline__ void stage_x3_pipe1(const char *sA, const char *sB,
+                                               f32x16 (&acc)[Geo<PREC_BF16X3>::FM][Geo<PREC_BF16X3>::FN],
+                                               int wm, int wn, int lane, F &&between)
+{
+    constexpr int PR = PREC_BF16X3;
+    constexpr int FM = Geo<PR>::FM, FN = Geo<PR>::FN;
+    bf16x8 a0[FM][2], b0[FN][2], a1[FM][2], b1[FN][2];
+    read_a<PR>(a0, sA, 1, 0, wm, lane);   // lo A
+    read_b<PR>(b0, sB, 0, 0, wn, lane);   // hi B
+    read_a<PR>(a0, sA, 0, 0, wm, lane);   // hi A
+    read_b<PR>(b0, sB, 1, 0, wn, lane);   // lo B
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[i][1], b0[j][0], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[i][0], b0[j][1], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_a<PR>(a1, sA, 1, 1, wm, lane);   // second half: lo A, hi B first
+    read_b<PR>(b1, sB, 0, 1, wn, lane);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[i][0], b0[j][0], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    read_a<PR>(a1, sA, 0, 1, wm, lane);
+    read_b<PR>(b1, sB, 1, 1, wn, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr int NM = 3 * FM * FN, GS = NM / NG;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        const int p = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
+        const int ta = p == 0 ? 1 : 0, tb = p == 1 ? 1 : 0;
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[i][ta], b1[j][tb], acc[i][j], 0, 0, 0);
+        if (m % GS == GS - 1) {
+            between(m / GS);
+#pragma unroll
+            for (int q = 0; q < GS; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -431,13 +672,225 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
     }
 }
 
+// Address of op(X)(r, k) for the two storage orders.
+template <bool KC>
+__device__ __forceinline__ const float *op_ptr(const float *X, int64_t ld, int64_t r, int64_t k)
+{
+    return KC ? X + r * ld + k : X + k * ld + r;
+}
+
+// Instruction interleave of one stage: all fragment reads first, then each
+// MFMA followed by a share of the split VALU work and, every few MFMAs, one
+// LDS write of the next stage.  (Hints to the scheduler; data dependences
+// still decide.)
+template <int PREC, int NKF = Geo<PREC>::KF>
+__device__ __forceinline__ void interleave_hint()
+{
+    using G = Geo<PREC>;
+    using C = Cfg<PREC>;
+    constexpr int NPROD = PREC == PREC_FP32 ? 8 : PREC == PREC_BF16X3 ? 3 : 6;
+    constexpr int NMFMA = G::FM * G::FN * NPROD * NKF;
+    constexpr int NREAD = (G::FM + G::FN) * C::terms * (C::entry_bytes / 16) * NKF;
+    // LDS writes of one stage: (rows of A + rows of B) x BK / 8 entries per
+    // term, spread over the workgroup
+    constexpr int NWRITE = (C::BM + C::BN) * (C::BK / 8) * C::terms * (C::entry_bytes / 16) / G::NT;
+    constexpr int VALU_PER = PREC == PREC_FP32 ? 0 : PREC == PREC_BF16X3 ? 4 : 2;
+    constexpr int W_EVERY = NMFMA / NWRITE > 0 ? NMFMA / NWRITE : 1;
+    __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
+#pragma unroll
+    for (int i = 0; i < NMFMA; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (VALU_PER > 0)
+            __builtin_amdgcn_sched_group_barrier(0x002, VALU_PER, 0);
+        if (i % W_EVERY == W_EVERY - 1)
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+}
+
+// K loop of one tile, software pipelined two stages deep: while the MFMAs of
+// stage s run from LDS buffer s%2, the registers holding stage s+1 (loaded
+// one stage earlier) are split into LDS buffer (s+1)%2, and stage s+2 is
+// being loaded into the other register set.  GUARD: every load is bounds
+// checked (edge tiles, unaligned operands); otherwise stages [0, K / BK) use
+// unguarded vector loads and only a partial last stage is guarded.
+template <int PREC, bool AKC, bool BKC, bool GUARD>
+__device__ __forceinline__ void k_loop2(const GemmDesc &d, int64_t row0, int64_t col0,
+                                        f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
+                                        char *smem, int wm, int wn, int lane)
+{
+    using C = Cfg<PREC>;
+    using G = Geo<PREC>;
+    constexpr int BK = C::BK;
+    using LA = Loader<C::BM, BK, G::NT, AKC>;
+    using LB = Loader<C::BN, BK, G::NT, BKC>;
+    LA la[2];
+    LB lb[2];
+    const int64_t nst = (d.K + BK - 1) / BK;
+    const int64_t nfull = GUARD ? 0 : d.K / BK;
+    if (nst == 0)
+        return;
+    if (!GUARD) {
+        la[0].init(d.lda);
+        lb[0].init(d.ldb);
+        la[1].init(d.lda);
+        lb[1].init(d.ldb);
+    }
+    auto fetch = [&](LA &a, LB &b, int64_t st) {
+        const int64_t k0 = st * BK;
+        if (st < nfull) {
+            a.load_fast(op_ptr<AKC>(d.A, d.lda, row0, k0), d.lda);
+            b.load_fast(op_ptr<BKC>(d.B, d.ldb, col0, k0), d.ldb);
+        } else {
+            a.load_guarded(d.A, d.lda, d.M, d.K, row0, k0);
+            b.load_guarded(d.B, d.ldb, d.N, d.K, col0, k0);
+        }
+    };
+    // one pipelined stage; register set P receives stage s+2, set Q (= 1-P)
+    // holds stage s+1
+    auto step = [&](auto pset, int64_t st, auto steady) {
+        constexpr int P = decltype(pset)::value, Q = 1 - P;
+        constexpr bool fast_next = decltype(steady)::value;
+        if constexpr (fast_next) {
+            const int64_t k2 = (st + 2) * BK;
+            la[P].load_fast(op_ptr<AKC>(d.A, d.lda, row0, k2), d.lda);
+            lb[P].load_fast(op_ptr<BKC>(d.B, d.ldb, col0, k2), d.ldb);
+        } else if (st + 2 < nst) {
+            fetch(la[P], lb[P], st + 2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        char *sc = smem + (int)(st & 1) * G::stage_bytes;        // stage being computed
+        char *sn = smem + (int)((st + 1) & 1) * G::stage_bytes;  // stage being filled
+        compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
+        if (fast_next || st + 1 < nst) {
+            la[Q].template store<PREC>(sn);
+            lb[Q].template store<PREC>(sn + G::a_bytes);
+        }
+        if constexpr (fast_next)
+            interleave_hint<PREC>();
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+    };
+    fetch(la[0], lb[0], 0);
+    la[0].template store<PREC>(smem);
+    lb[0].template store<PREC>(smem + G::a_bytes);
+    if (nst > 1)
+        fetch(la[1], lb[1], 1);
+    __syncthreads();
+    int64_t s = 0;
+    // steady state: the stages fetched (s+2, s+3) are full ones
+    for (; s + 3 < nfull; s += 2) {
+        step(std::integral_constant<int, 0>{}, s, std::true_type{});
+        step(std::integral_constant<int, 1>{}, s + 1, std::true_type{});
+    }
+    for (; s < nst; s += 2) {
+        step(std::integral_constant<int, 0>{}, s, std::false_type{});
+        if (s + 1 < nst)
+            step(std::integral_constant<int, 1>{}, s + 1, std::false_type{});
+    }
+}
+
+// K loop, one register stage (PIPE 1, BK = 32): the loads of stage s+1 are
+// issued at the top of stage s, the first 16-k half of stage s computes while
+// they are in flight, and the split/LDS writes of stage s+1 are interleaved
+// with the MFMAs of the second half.
+template <int PREC, bool AKC, bool BKC, bool GUARD>
+__device__ __forceinline__ void k_loop1(const GemmDesc &d, int64_t row0, int64_t col0,
+                                        f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
+                                        char *smem, int wm, int wn, int lane)
+{
+    using C = Cfg<PREC>;
+    using G = Geo<PREC>;
+    constexpr int BK = C::BK;
+    static_assert(G::KF == 2, "PIPE 1 splits a stage into two 16-k halves");
+    Loader<C::BM, BK, G::NT, AKC> la;
+    Loader<C::BN, BK, G::NT, BKC> lb;
+    const int64_t nst = (d.K + BK - 1) / BK;
+    const int64_t nfull = GUARD ? 0 : d.K / BK;
+    if (nst == 0)
+        return;
+    if (!GUARD) {
+        la.init(d.lda);
+        lb.init(d.ldb);
+    }
+    if (nfull > 0) {
+        la.load_fast(op_ptr<AKC>(d.A, d.lda, row0, 0), d.lda);
+        lb.load_fast(op_ptr<BKC>(d.B, d.ldb, col0, 0), d.ldb);
+    } else {
+        la.load_guarded(d.A, d.lda, d.M, d.K, row0, 0);
+        lb.load_guarded(d.B, d.ldb, d.N, d.K, col0, 0);
+    }
+    la.template store<PREC>(smem);
+    lb.template store<PREC>(smem + G::a_bytes);
+    __syncthreads();
+    int64_t s = 0;
+    for (; s + 1 < nfull; ++s) {
+        const int64_t k1 = (s + 1) * BK;
+        la.load_fast(op_ptr<AKC>(d.A, d.lda, row0, k1), d.lda);
+        lb.load_fast(op_ptr<BKC>(d.B, d.ldb, col0, k1), d.ldb);
+        __builtin_amdgcn_sched_barrier(0);
+        char *sc = smem + (int)(s & 1) * G::stage_bytes;
+        char *sn = smem + (int)((s + 1) & 1) * G::stage_bytes;
+        // entries of the next stage: A rows then B rows, one per MFMA group
+        constexpr int EA = decltype(la)::UPT * decltype(la)::R;
+        constexpr int EB_ = decltype(lb)::UPT * decltype(lb)::R;
+        auto between = [&](int g) {
+            if (g < EA)
+                la.template store_entry<PREC>(sn, g / decltype(la)::R, g % decltype(la)::R);
+            else
+                lb.template store_entry<PREC>(sn + G::a_bytes, (g - EA) / decltype(lb)::R,
+                                              (g - EA) % decltype(lb)::R);
+        };
+        if constexpr (PREC == PREC_BF16X3) {
+            stage_x3_pipe1<EA + EB_>(sc, sc + G::a_bytes, acc, wm, wn, lane, between);
+        } else {
+            compute_stage<PREC, 0, 1>(sc, sc + G::a_bytes, acc, wm, wn, lane);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_half_interleaved<PREC, 1, EA + EB_>(sc, sc + G::a_bytes, acc, wm, wn, lane,
+                                                        between);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+    }
+    for (; s < nst; ++s) {
+        const bool more = s + 1 < nst;
+        if (more) {
+            const int64_t k1 = (s + 1) * BK;
+            if (s + 1 < nfull) {
+                la.load_fast(op_ptr<AKC>(d.A, d.lda, row0, k1), d.lda);
+                lb.load_fast(op_ptr<BKC>(d.B, d.ldb, col0, k1), d.ldb);
+            } else {
+                la.load_guarded(d.A, d.lda, d.M, d.K, row0, k1);
+                lb.load_guarded(d.B, d.ldb, d.N, d.K, col0, k1);
+            }
+        }
+        char *sc = smem + (int)(s & 1) * G::stage_bytes;
+        char *sn = smem + (int)((s + 1) & 1) * G::stage_bytes;
+        compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
+        if (more) {
+            la.template store<PREC>(sn);
+            lb.template store<PREC>(sn + G::a_bytes);
+        }
+        __syncthreads();
+    }
+}
+
+template <int PREC, bool AKC, bool BKC, bool GUARD>
+__device__ __forceinline__ void k_loop(const GemmDesc &d, int64_t row0, int64_t col0,
+                                       f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
+                                       char *smem, int wm, int wn, int lane)
+{
+    if constexpr (Cfg<PREC>::PIPE == 1)
+        k_loop1<PREC, AKC, BKC, GUARD>(d, row0, col0, acc, smem, wm, wn, lane);
+    else
+        k_loop2<PREC, AKC, BKC, GUARD>(d, row0, col0, acc, smem, wm, wn, lane);
+}
+
 template <int PREC, bool AKC, bool BKC>
 __device__ __forceinline__ void gemm_tile(const GemmDesc &d, int tm, int tn, char *smem,
                                           double *red)
 {
     using C = Cfg<PREC>;
     using G = Geo<PREC>;
-    constexpr int BK = C::BK;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w / C::WN, wn = w % C::WN;
     const int64_t row0 = (int64_t)tm * C::BM, col0 = (int64_t)tn * C::BN;
@@ -449,45 +902,18 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &d, int tm, int tn, cha
         for (int j = 0; j < G::FN; ++j)
             acc[i][j] = f32x16{};
 
-    Loader<C::BM, BK, G::NT, AKC> la;
-    Loader<C::BN, BK, G::NT, BKC> lb;
-    const int64_t nst = (d.K + BK - 1) / BK;
-    const bool in_m = row0 + C::BM <= d.M, in_n = col0 + C::BN <= d.N;
-    const bool va = d.vec_a && in_m, vb = d.vec_b && in_n;
-
-    if (nst > 0) {
-        const bool full0 = BK <= d.K;
-        la.load(d.A, d.lda, d.M, d.K, row0, 0, va && full0);
-        lb.load(d.B, d.ldb, d.N, d.K, col0, 0, vb && full0);
-        la.template store<PREC>(smem);
-        lb.template store<PREC>(smem + G::a_bytes);
-        __syncthreads();
-        for (int64_t s = 0; s < nst; ++s) {
-            const int cur = (int)(s & 1);
-            const bool more = s + 1 < nst;
-            if (more) {
-                const int64_t k0 = (s + 1) * BK;
-                const bool full = k0 + BK <= d.K;
-                la.load(d.A, d.lda, d.M, d.K, row0, k0, va && full);
-                lb.load(d.B, d.ldb, d.N, d.K, col0, k0, vb && full);
-            }
-            char *sc = smem + cur * G::stage_bytes;        // stage being computed
-            char *sn = smem + (cur ^ 1) * G::stage_bytes;  // stage being filled
-            compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
-            if (more) {
-                la.template store<PREC>(sn);
-                lb.template store<PREC>(sn + G::a_bytes);
-            }
-            __syncthreads();
-        }
-    }
+    const bool interior = row0 + C::BM <= d.M && col0 + C::BN <= d.N && d.vec_a && d.vec_b;
+    if (interior)
+        k_loop<PREC, AKC, BKC, false>(d, row0, col0, acc, smem, wm, wn, lane);
+    else
+        k_loop<PREC, AKC, BKC, true>(d, row0, col0, acc, smem, wm, wn, lane);
     epilogue<PREC>(d, acc, tm, tn, wm, wn, lane, red);
 }
 
 // ---------------------------------------------------------------- kernels
 
 template <int PREC, bool AKC, bool BKC>
-__global__ void __launch_bounds__(Geo<PREC>::NT, 1) gemm_kernel(GemmDesc d)
+__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(GemmDesc d)
 {
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
@@ -500,7 +926,7 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, 1) gemm_kernel(GemmDesc d)
 // Persistent grouped kernel: workgroup b runs items b, b + grid, ...; each
 // item is one tile of one problem, computed exactly as gemm_kernel would.
 template <int PREC, bool AKC, bool BKC>
-__global__ void __launch_bounds__(Geo<PREC>::NT, 1)
+__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC)
     gemm_grouped_kernel(const GemmDesc *__restrict__ probs, const GroupItem *__restrict__ items,
                         int num_items)
 {
