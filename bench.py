@@ -108,6 +108,99 @@ def cpu_baseline(A, B, C_gpu, budget_s: float, seed: int = 203):
     }, float(est), tiles
 
 
+def polar_section(la, torch, n=16384, lo=1e-6, seeds=(301, 302, 303)):
+    """Polar factorisation of an n x n A = Q diag(s) V^T (cond 1/lo), AUTO policy
+    (6xBF16 preconditioning, 3xBF16 Newton-Schulz and H) and all-FP32-MFMA."""
+    import la_inputs
+
+    t0 = time.perf_counter()
+    A, Q, s, V = la_inputs.polar_case_torch(n, n, lo, seeds)
+    del Q, V
+    torch.cuda.empty_cache()
+    Ad = torch.from_numpy(A).to("cuda:0")
+    U = torch.empty_like(Ad)
+    H = torch.empty_like(Ad)
+    print(f"[bench] polar inputs {n}x{n} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    out = {"workload": f"polar {n}x{n} FP32, A = Q diag(s) V^T, Haar Q, V, s log-uniform "
+                       f"in [{lo:g}, 1], seeds {seeds[0]}/{seeds[1]}/{seeds[2]}"}
+    policies = {"auto": {}, "fp32": dict(prec_precond=1, prec_ns=1, prec_h=1)}
+    for name, opts in policies.items():
+        la.polar(Ad, U=U, H=H, **opts)          # warm-up (same work)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, info = la.polar(Ad, U=U, H=H, **opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        k = info["iters_precond"] + info["iters_ns"]
+        alg = (3.0 * k + 2.0) * float(n) ** 3          # Gram n^3 + update 2n^3 per step, H 2n^3
+        paper_eq = 2.0 * (2 * k + 1) * float(n) ** 3   # "about 50 matmuls" convention
+        out[name] = {"seconds": round(dt, 3), "iters_precond": info["iters_precond"],
+                     "iters_ns": info["iters_ns"], "tflops_algorithmic": round(alg / dt / 1e12, 1),
+                     "tflops_paper_equivalent": round(paper_eq / dt / 1e12, 1)}
+        print(f"[bench] polar {name}: {dt:.2f} s, {out[name]}", file=sys.stderr, flush=True)
+    out["speedup_auto_vs_fp32"] = round(out["fp32"]["seconds"] / out["auto"]["seconds"], 2)
+    return out
+
+
+def serving_section(la, torch, rate=100.0, duration=10.0, pool_size=48, seed=401):
+    """Poisson stream of square polar requests (n log-uniform in [128, 4096],
+    cond 10^U(1,6)) against the continuous-batching server; p50/p99 latency from
+    submit to completed poll."""
+    import la_inputs
+
+    t0 = time.perf_counter()
+    g = la_inputs.rng(seed + 1)
+    sizes = la_inputs.serve_sizes(pool_size, seed + 2)
+    conds = 10.0 ** g.uniform(1.0, 6.0, size=pool_size)
+    pool = [la_inputs.polar_case_torch(int(n), int(n), 1.0 / c,
+                                       (seed * 1000 + 3 * i, seed * 1000 + 3 * i + 1,
+                                        seed * 1000 + 3 * i + 2))[0]
+            for i, (n, c) in enumerate(zip(sizes, conds))]
+    torch.cuda.empty_cache()
+    stream = la_inputs.serve_stream(rate, duration, seed, pool_size)
+    print(f"[bench] serving pool of {pool_size} in {time.perf_counter() - t0:.1f} s, "
+          f"{len(stream)} arrivals", file=sys.stderr, flush=True)
+    lat = []
+    flops = 0.0
+    with la.Server(16 << 30, max_slots=64) as srv:
+        # warm-up: one request of each size class compiles nothing but touches the code
+        w = srv.submit(pool[0])
+        while srv.poll(w) is None:
+            time.sleep(0.001)
+        pending = {}
+        start = time.perf_counter()
+        i = 0
+        while i < len(stream) or pending:
+            now = time.perf_counter() - start
+            while i < len(stream) and stream[i][0] <= now:
+                A = pool[stream[i][1]]
+                rid = srv.submit(A)
+                pending[rid] = (time.perf_counter(), A.shape[0])
+                i += 1
+            for rid in list(pending):
+                r = srv.poll(rid, want_h=False)
+                if r is not None:
+                    t_sub, n = pending.pop(rid)
+                    lat.append(time.perf_counter() - t_sub)
+                    k = r[3]["iters_precond"] + r[3]["iters_ns"]
+                    flops += (3.0 * k + 2.0) * float(n) ** 3
+            time.sleep(0.0002)
+        wall = time.perf_counter() - start
+        st = srv.stats()
+    lat_ms = np.array(lat) * 1e3
+    return {"workload": f"Poisson arrivals at {rate:g} req/s for {duration:g} s, square n "
+                        f"log-uniform in [128, 4096] (x64), cond 10^U(1,6), pool of {pool_size} "
+                        f"(seed {seed}), AUTO policy",
+            "requests": int(len(lat)), "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+            "mean_ms": round(float(lat_ms.mean()), 2),
+            "throughput_req_s": round(len(lat) / wall, 1),
+            "tflops_algorithmic": round(flops / wall / 1e12, 2),
+            "ticks": int(st["ticks"]), "gpu_busy_frac": round(st["busy_seconds"] / wall, 3),
+            "arena_high_water_gib": round(st["arena_high_water"] / 2 ** 30, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +208,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-polar", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -174,7 +269,7 @@ def main():
         PEAK_BF16 / 6.0 if head == "BF16X6" else PEAK_FP32)
     traffic = load_traffic() if head == "BF16X3" else None
     out = {
-        "metric": "FP32-accurate GEMM TFLOP/s (3xBF16 split on BF16 MFMA, FP32 accumulate)",
+        "metric": "FP32-accurate GEMM/polar TFLOP/s (3xBF16 vs fp32 MFMA); serve p50/p99 ms",
         "value": round(tflops, 2),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -212,6 +307,13 @@ def main():
         out["cpu_baseline"] = cb
         out["sampled_normwise_error"] = err
         out["sampled_tiles"] = tiles
+    del Ad, Bd, Cd, A, B
+    torch.cuda.empty_cache()
+    if not args.no_polar and args.only is None:
+        out["polar"] = polar_section(la, torch)
+        torch.cuda.empty_cache()
+    if not args.no_serving and args.only is None:
+        out["serving"] = serving_section(la, torch)
     print(json.dumps(out), flush=True)
 
 

@@ -55,7 +55,8 @@ typedef enum {
  *            BF16 matrix cores (each product exact in FP32).
  *   BF16X6 : x = hi + mid + lo (three bf16 terms, 24 significant bits);
  *            products hh + hm + mh + mm + hl + lh.
- *   AUTO   : la_gemm -> BF16X3; la_polar -> per phase (see la_polar_opts).
+ *   AUTO   : la_gemm -> BF16X3; la_polar -> per phase (see la_polar_opts):
+ *            preconditioning and H at BF16X6, Newton-Schulz at BF16X3.
  * The paper's TPU "fp32" matmul is itself a bf16-based emulation at about
  * six times the bf16 cost (section II); BF16X6 is the analogue here. */
 typedef enum {
@@ -108,7 +109,7 @@ typedef struct {
     int max_iter;     /* cap on Newton-Schulz steps                     [100]   */
     int prec_precond; /* la_precision of the preconditioning GEMMs [AUTO=BF16X6] */
     int prec_ns;      /* la_precision of the Newton-Schulz GEMMs   [AUTO=BF16X3] */
-    int prec_h;       /* la_precision of H = sym(U^T A)            [AUTO=BF16X3] */
+    int prec_h;       /* la_precision of H = sym(U^T A)            [AUTO=BF16X6] */
     int polish;       /* 1: one extra Newton-Schulz step at BF16X6 after the
                          stop test                                          [0] */
     int no_stagnation;/* 1: disable the stagnation stop                     [0] */

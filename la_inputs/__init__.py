@@ -132,3 +132,25 @@ def serve_pool(pool_size: int, seed: int, n_lo: int = 128, n_hi: int = 4096):
         base = seed * 1000 + 3 * i
         cases.append(polar_case(int(n), int(n), 1.0 / float(c), (base, base + 1, base + 2)))
     return cases
+
+
+def polar_case_torch(m: int, n: int, lo: float, seeds, device="cuda"):
+    """Same recipe as polar_case (A = Q diag(s) V^T, Haar Q and V from the QR
+    of seeded numpy Gaussians, sign-fixed), with the QR and the product done
+    in float64 by torch on `device` so that large sizes are practical.
+    Returns (A32 host float32, Q dev float64, s host float64, V dev float64)."""
+    import torch
+
+    def orth(rows, cols, seed):
+        g = torch.from_numpy(rng(seed).standard_normal(size=(rows, cols))).to(device)
+        q, r = torch.linalg.qr(g, mode="reduced")
+        d = torch.sign(torch.diagonal(r))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+
+    Q = orth(m, n, seeds[0])
+    V = orth(n, n, seeds[1])
+    s = singular_values(n, lo, seeds[2])
+    sd = torch.from_numpy(s).to(device)
+    A = ((Q * sd[None, :]) @ V.T.contiguous()).to(torch.float32).cpu().numpy()
+    return A, Q, s, V

@@ -130,6 +130,18 @@ __global__ void __launch_bounds__(kThreads) reduce_fixed_kernel(const double *__
         out[0] = s;
 }
 
+__global__ void __launch_bounds__(kThreads) reduce_grouped_kernel(const ReduceItem *__restrict__ items)
+{
+    __shared__ double sh[kThreads / 64];
+    const ReduceItem it = items[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < it.count; i += kThreads)
+        acc += it.parts[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0)
+        it.out[0] = s;
+}
+
 __global__ void scale_kernel(const float *__restrict__ X, int64_t ldx, float *__restrict__ Y,
                              int64_t ldy, int64_t m, int64_t n, double nrm)
 {
@@ -208,6 +220,14 @@ hipError_t launch_sumsq(const float *X, int64_t m, int64_t n, int64_t ld, double
 hipError_t launch_reduce_fixed(const double *parts, int64_t count, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_fixed_kernel, dim3(1), dim3(kThreads), 0, s, parts, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_grouped(const ReduceItem *items, int n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(reduce_grouped_kernel, dim3(n), dim3(kThreads), 0, s, items);
     return hipGetLastError();
 }
 

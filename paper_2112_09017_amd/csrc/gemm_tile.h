@@ -444,7 +444,7 @@ __device__ __forceinline__ void compute_half_interleaved(const char *sA, const c
                             sB + frag_off<C::BN, KF, EB>(0, wn * FN + j, KK, lane))[h];
             }
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int m = 0; m < NM; ++m) {
             const int e = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][e >> 2][e & 3],
@@ -480,19 +480,21 @@ __device__ __forceinline__ void compute_half_interleaved(const char *sA, const c
             have_b[tb] = true;
         }
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int m = 0; m < NM; ++m) {
             const int p = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][P::a[p]], b[j][P::b[p]],
                                                                acc[i][j], 0, 0, 0);
             if (m % GS == GS - 1) {
                 between(m / GS);
+                // split work of one entry: ~6 VALU per 2 values per term
+                constexpr int VPER = (12 * T + GS - 1) / GS;
 #pragma unroll
                 for (int q = 0; q < GS; ++q) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, VPER, 0);
                 }
-                __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, T, 0);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -564,7 +566,7 @@ __device__ __forceinline__ void stage_x3_pipe1(const char *sA, const char *sB,
     read_b<PR>(b1, sB, 1, 1, wn, lane);
     __builtin_amdgcn_sched_barrier(0);
     constexpr int NM = 3 * FM * FN, GS = NM / NG;
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int m = 0; m < NM; ++m) {
         const int p = m / (FM * FN), i = (m / FN) % FM, j = m % FN;
         const int ta = p == 0 ? 1 : 0, tb = p == 1 ? 1 : 0;
@@ -760,13 +762,23 @@ __device__ __forceinline__ void k_loop2(const GemmDesc &d, int64_t row0, int64_t
         __builtin_amdgcn_sched_barrier(0);
         char *sc = smem + (int)(st & 1) * G::stage_bytes;        // stage being computed
         char *sn = smem + (int)((st + 1) & 1) * G::stage_bytes;  // stage being filled
-        compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
-        if (fast_next || st + 1 < nst) {
-            la[Q].template store<PREC>(sn);
-            lb[Q].template store<PREC>(sn + G::a_bytes);
+        if constexpr (fast_next && G::KF == 1) {
+            constexpr int EA = LA::UPT * LA::R, EB_ = LB::UPT * LB::R;
+            compute_half_interleaved<PREC, 0, EA + EB_>(
+                sc, sc + G::a_bytes, acc, wm, wn, lane, [&](int g) {
+                    if (g < EA)
+                        la[Q].template store_entry<PREC>(sn, g / LA::R, g % LA::R);
+                    else
+                        lb[Q].template store_entry<PREC>(sn + G::a_bytes, (g - EA) / LB::R,
+                                                         (g - EA) % LB::R);
+                });
+        } else {
+            compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
+            if (fast_next || st + 1 < nst) {
+                la[Q].template store<PREC>(sn);
+                lb[Q].template store<PREC>(sn + G::a_bytes);
+            }
         }
-        if constexpr (fast_next)
-            interleave_hint<PREC>();
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
     };

@@ -23,11 +23,6 @@
 
 #include "la_internal.h"
 
-struct la_context {
-    int device;
-    int num_cus;
-};
-
 namespace la {
 
 static thread_local char g_err[512];
@@ -110,7 +105,10 @@ la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan 
     }
     p.prec_pre = resolve(o.prec_precond, PREC_BF16X6);
     p.prec_ns = resolve(o.prec_ns, PREC_BF16X3);
-    p.prec_h = resolve(o.prec_h, PREC_BF16X3);
+    // H = sym(U^T A) is one product (about 2 of the ~85 N^3 of a polar) but its
+    // error enters the residual directly: at 3xBF16 it alone is about
+    // 2^-16 ||A||_F, so AUTO computes it at 6xBF16.
+    p.prec_h = resolve(o.prec_h, PREC_BF16X6);
     // eq. (a_def) and the recurrence of eq. (RogueScalar): the number of
     // preconditioning steps is fixed before any matrix work.
     p.a = 1.5 * sqrt(3.0) - p.s_minus;

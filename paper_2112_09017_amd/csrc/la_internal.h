@@ -8,6 +8,11 @@
 
 #include "../../include/la.h"
 
+struct la_context {
+    int device;
+    int num_cus;
+};
+
 namespace la {
 
 // Resolved product arithmetic (la_precision without AUTO).
@@ -83,6 +88,15 @@ hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s);
 hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n,
                                     float alpha, float gamma, float *out,
                                     int64_t ldo, hipStream_t s);
+
+// Grouped fixed-order FP64 reduction: one workgroup per item,
+// out[0] = sum of parts[0..count) (same order as launch_reduce_fixed).
+struct ReduceItem {
+    const double *parts;
+    int64_t count;
+    double *out;
+};
+hipError_t launch_reduce_grouped(const ReduceItem *items_dev, int n, hipStream_t s);
 
 // Polar building blocks shared by la_polar and the server.
 struct PolarPlan {

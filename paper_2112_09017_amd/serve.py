@@ -44,6 +44,8 @@ class Server:
 
     def poll(self, rid: int, want_h: bool = True):
         """None while pending; else (status, U, H or None, info dict)."""
+        if rid not in self._shapes:     # unknown here: let the library say so
+            check(lib().la_serve_poll(self._srv, rid, None, None, None, None))
         m, n = self._shapes[rid]
         U = np.empty((m, n), np.float32)
         H = np.empty((n, n), np.float32) if want_h else None

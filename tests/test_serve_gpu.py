@@ -1,0 +1,148 @@
+"""Continuous-batching server (la_serve_*) on the GPU.
+
+* a request's factors are bitwise identical alone and in a mix of sizes and
+  phases (every tile is computed the same way whatever shares the launch);
+* requests overlap on the device (shared ticks) and are admitted by HBM
+  footprint (a tight arena forces waiting, never overflow);
+* every result meets the polar tolerances and matches the FP64 oracle's H;
+* error paths: non-finite input fails alone, too-large and queue-full are
+  rejected at submit, unknown and twice-polled ids are reported.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import la_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def la():
+    import paper_2112_09017_amd as la
+    la.lib()
+    return la
+
+
+def wait_all(srv, ids, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(ids):
+        for i in ids:
+            if i in out:
+                continue
+            r = srv.poll(i)
+            if r is not None:
+                out[i] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(ids) - len(out)} requests pending")
+        time.sleep(0.001)
+    return out
+
+
+SIZES = [(128, 128, 1e-2), (192, 192, 1e-3), (320, 320, 1e-4), (640, 256, 1e-3),
+         (512, 512, 1e-5), (256, 128, 1e-2)]
+
+
+def cases():
+    return [la_inputs.polar_case(m, n, lo, seeds=(900 + i, 910 + i, 920 + i))
+            for i, (m, n, lo) in enumerate(SIZES)]
+
+
+def test_mix_equals_alone_and_meets_tolerance(la):
+    cs = cases()
+    with la.Server(1 << 30, max_slots=16) as srv:
+        ids = [srv.submit(c.A32) for c in cs]
+        mix = wait_all(srv, ids)
+        st = srv.stats()
+    total_iters = sum(mix[i][3]["iters_precond"] + mix[i][3]["iters_ns"] for i in ids)
+    print("stats", st, "total iterations", total_iters)
+    assert st["completed"] == len(cs)
+    assert st["ticks"] < total_iters          # requests shared ticks (overlap)
+    for c, i in zip(cs, ids):
+        status, U, H, info = mix[i]
+        assert status == la.Status.OK
+        with la.Server(1 << 30) as alone:
+            j = alone.submit(c.A32)
+            s2, U2, H2, info2 = wait_all(alone, [j])[j]
+        assert np.array_equal(U, U2) and np.array_equal(H, H2), c.A32.shape
+        assert info == info2
+        A = c.A32.astype(np.float64)
+        U64, H64 = U.astype(np.float64), H.astype(np.float64)
+        n = U.shape[1]
+        orth = np.linalg.norm(U64.T @ U64 - np.eye(n)) / math.sqrt(n)
+        resid = np.linalg.norm(A - U64 @ H64) / np.linalg.norm(A)
+        _, Ho, _ = oracle.polar(A)
+        dh = np.linalg.norm(H64 - Ho) / np.linalg.norm(A)
+        print(c.A32.shape, info, orth, resid, dh)
+        assert orth <= TOL and resid <= TOL and dh <= TOL
+
+
+def test_tight_arena_admission(la):
+    """An arena that holds two 512 x 512 requests at a time still serves six."""
+    cs = [la_inputs.polar_case(512, 512, 1e-3, seeds=(930 + i, 940 + i, 950 + i))
+          for i in range(6)]
+    reserve = 8 << 20                                   # server descriptors
+    per = 4 * (3 * 512 * 512 + 512 * 512) + (1 << 16)   # one 512 x 512 request
+    per_big = 4 * (3 * 2048 * 2048 + 2048 * 2048) + (1 << 16)
+    # the 2048 request takes most of the arena, so the small ones wait for it
+    arena = reserve + per_big + per + (1 << 20)
+    with la.Server(arena, max_slots=8) as srv:
+        big = la_inputs.polar_case(2048, 2048, 1e-2, seeds=(960, 961, 962))
+        ids = [srv.submit(big.A32)] + [srv.submit(c.A32) for c in cs]
+        out = wait_all(srv, ids, timeout=300)
+        st = srv.stats()
+    print(st, "arena", arena, "2048 footprint", per_big)
+    assert st["completed"] == 7
+    assert st["arena_high_water"] <= arena
+    for i in ids:
+        assert out[i][0] == la.Status.OK
+
+
+def test_error_paths(la):
+    good = la_inputs.polar_case(128, 128, 1e-2, seeds=(970, 971, 972))
+    with la.Server(256 << 20, max_slots=4, max_queue=3) as srv:
+        with pytest.raises(la.LAError) as e:
+            srv.submit(np.ones((8192, 8192), np.float32))
+        assert e.value.status == la.Status.TOO_LARGE
+        with pytest.raises(la.LAError) as e:
+            srv.submit(np.ones((3, 5), np.float32))
+        assert e.value.status == la.Status.SHAPE
+        bad = srv.submit(np.full((64, 64), np.nan, np.float32))
+        ok = srv.submit(good.A32)
+        out = wait_all(srv, [bad, ok])
+        assert out[bad][0] == la.Status.NONFINITE
+        assert out[ok][0] == la.Status.OK
+        with pytest.raises(la.LAError) as e:
+            srv.poll(ok)                      # already collected
+        assert e.value.status == la.Status.UNKNOWN_REQUEST
+        capped = srv.submit(good.A32, max_iter=1)
+        r = wait_all(srv, [capped])[capped]
+        assert r[0] == la.Status.NOT_CONVERGED and r[3]["iters_ns"] == 1
+    with la.Server(256 << 20, max_slots=1, max_queue=2) as srv:
+        big = la_inputs.polar_case(1024, 1024, 1e-2, seeds=(973, 974, 975))
+        ids = []
+        with pytest.raises(la.LAError) as e:
+            for _ in range(64):
+                ids.append(srv.submit(big.A32))
+        assert e.value.status == la.Status.QUEUE_FULL
+        assert srv.poll(ids[-1]) is None      # still pending (NOT_READY)
+    # leaving the with-block destroyed the server with requests pending
+
+
+def test_matches_la_polar_tolerances_for_tall(la):
+    c = la_inputs.polar_case(1500, 300, 1e-4, seeds=(980, 981, 982))
+    with la.Server(1 << 30) as srv:
+        i = srv.submit(c.A32)
+        st, U, H, info = wait_all(srv, [i])[i]
+    A = c.A32.astype(np.float64)
+    U, H = U.astype(np.float64), H.astype(np.float64)
+    orth = np.linalg.norm(U.T @ U - np.eye(300)) / math.sqrt(300)
+    resid = np.linalg.norm(A - U @ H) / np.linalg.norm(A)
+    print(info, orth, resid)
+    assert st == la.Status.OK and orth <= TOL and resid <= TOL
