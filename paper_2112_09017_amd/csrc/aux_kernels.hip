@@ -11,26 +11,28 @@ namespace la {
 hipError_t launch_gemm_fp32(const GemmDesc &d, hipStream_t s);
 hipError_t launch_gemm_x3(const GemmDesc &d, hipStream_t s);
 hipError_t launch_gemm_x6(const GemmDesc &d, hipStream_t s);
-hipError_t launch_grouped_fp32(int, int, const GemmDesc *, const GroupItem *, int, int,
+hipError_t launch_grouped_fp32(int, int, int, const GemmDesc *, const GroupItem *, int, int,
                                hipStream_t);
-hipError_t launch_grouped_x3(int, int, const GemmDesc *, const GroupItem *, int, int,
+hipError_t launch_grouped_x3(int, int, int, const GemmDesc *, const GroupItem *, int, int,
                              hipStream_t);
-hipError_t launch_grouped_x6(int, int, const GemmDesc *, const GroupItem *, int, int,
+hipError_t launch_grouped_x6(int, int, int, const GemmDesc *, const GroupItem *, int, int,
                              hipStream_t);
-int tile_m_fp32();
-int tile_n_fp32();
-int tile_m_x3();
-int tile_n_x3();
-int tile_m_x6();
-int tile_n_x6();
+int tile_m_fp32(int);
+int tile_n_fp32(int);
+int tile_m_x3(int);
+int tile_n_x3(int);
+int tile_m_x6(int);
+int tile_n_x6(int);
 
-int tile_m(int prec)
+int tile_m(int prec, int small)
 {
-    return prec == PREC_FP32 ? tile_m_fp32() : prec == PREC_BF16X3 ? tile_m_x3() : tile_m_x6();
+    return prec == PREC_FP32 ? tile_m_fp32(small)
+                             : prec == PREC_BF16X3 ? tile_m_x3(small) : tile_m_x6(small);
 }
-int tile_n(int prec)
+int tile_n(int prec, int small)
 {
-    return prec == PREC_FP32 ? tile_n_fp32() : prec == PREC_BF16X3 ? tile_n_x3() : tile_n_x6();
+    return prec == PREC_FP32 ? tile_n_fp32(small)
+                             : prec == PREC_BF16X3 ? tile_n_x3(small) : tile_n_x6(small);
 }
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -39,7 +41,14 @@ void gemm_finalize(GemmDesc &d, int prec)
 {
     d.vec_a = aligned16(d.A) && (d.lda % 4 == 0);
     d.vec_b = aligned16(d.B) && (d.ldb % 4 == 0);
-    const int bm = tile_m(prec), bn = tile_n(prec);
+    // small tiles when large ones would leave most CUs idle
+    {
+        const int64_t lm = (d.M + tile_m(prec) - 1) / tile_m(prec);
+        const int64_t ln = (d.N + tile_n(prec) - 1) / tile_n(prec);
+        const int64_t large = d.gram ? ln * (ln + 1) / 2 : lm * ln;
+        d.small = large < 128 ? 1 : 0;
+    }
+    const int bm = tile_m(prec, d.small), bn = tile_n(prec, d.small);
     d.tiles_m = (int)((d.M + bm - 1) / bm);
     d.tiles_n = (int)((d.N + bn - 1) / bn);
     if (d.gram)
@@ -60,14 +69,17 @@ hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s)
     }
 }
 
-hipError_t launch_gemm_grouped(int prec, int akc, int bkc, const GemmDesc *probs,
+hipError_t launch_gemm_grouped(int prec, int akc, int bkc, int small, const GemmDesc *probs,
                                const GroupItem *items, int num_items, int grid_size,
                                hipStream_t s)
 {
     switch (prec) {
-    case PREC_FP32: return launch_grouped_fp32(akc, bkc, probs, items, num_items, grid_size, s);
-    case PREC_BF16X3: return launch_grouped_x3(akc, bkc, probs, items, num_items, grid_size, s);
-    case PREC_BF16X6: return launch_grouped_x6(akc, bkc, probs, items, num_items, grid_size, s);
+    case PREC_FP32:
+        return launch_grouped_fp32(akc, bkc, small, probs, items, num_items, grid_size, s);
+    case PREC_BF16X3:
+        return launch_grouped_x3(akc, bkc, small, probs, items, num_items, grid_size, s);
+    case PREC_BF16X6:
+        return launch_grouped_x6(akc, bkc, small, probs, items, num_items, grid_size, s);
     default: return hipErrorInvalidValue;
     }
 }

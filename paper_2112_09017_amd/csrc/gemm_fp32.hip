@@ -1,5 +1,6 @@
-// Instantiates the tile GEMM (gemm_tile.h) for one precision; kept in its own
-// translation unit so the three precisions compile in parallel.
+// Instantiates the tile GEMM (gemm_tile.h) for one precision, both tile
+// classes; kept in its own translation unit so the precisions compile in
+// parallel.
 #include "gemm_tile.h"
 
 namespace la {
@@ -9,13 +10,13 @@ hipError_t launch_gemm_fp32(const GemmDesc &d, hipStream_t s)
     return dev::launch_t<PREC_FP32>(d, s);
 }
 
-hipError_t launch_grouped_fp32(int akc, int bkc, const GemmDesc *probs, const GroupItem *items,
-                             int num_items, int grid_size, hipStream_t s)
+hipError_t launch_grouped_fp32(int akc, int bkc, int small, const GemmDesc *probs,
+                             const GroupItem *items, int num_items, int grid_size, hipStream_t s)
 {
-    return dev::launch_grouped_t<PREC_FP32>(akc, bkc, probs, items, num_items, grid_size, s);
+    return dev::launch_grouped_t<PREC_FP32>(akc, bkc, small, probs, items, num_items, grid_size, s);
 }
 
-int tile_m_fp32() { return dev::Cfg<PREC_FP32>::BM; }
-int tile_n_fp32() { return dev::Cfg<PREC_FP32>::BN; }
+int tile_m_fp32(int small) { return small ? dev::Cfg<PREC_FP32 | dev::kSmall>::BM : dev::Cfg<PREC_FP32>::BM; }
+int tile_n_fp32(int small) { return small ? dev::Cfg<PREC_FP32 | dev::kSmall>::BN : dev::Cfg<PREC_FP32>::BN; }
 
 }  // namespace la

@@ -50,6 +50,11 @@ constexpr int kXcds = 8;
 #ifndef LA_X3_WN
 #define LA_X3_WN 2
 #endif
+// A kernel's PREC template argument is the arithmetic (PREC_FP32 / _BF16X3 /
+// _BF16X6) plus kSmall for the 128 x 128 tile variant.
+constexpr int kSmall = 16;
+constexpr int base_prec(int P) { return P & 15; }
+
 template <int PREC> struct Cfg;
 // PIPE 1: one register stage, BK = 32, the next stage's split/stores run in
 // the second 16-k half of the current stage.  PIPE 2: two register stages,
@@ -64,6 +69,22 @@ template <> struct Cfg<PREC_BF16X3> {
 };
 template <> struct Cfg<PREC_BF16X6> {
     static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2;
+    static constexpr int terms = 3, entry_bytes = 16;
+};
+// 128 x 128 tiles (64 x 64 per wave), two workgroups per CU: problems too
+// small to give every CU a 256 x 256 tile.  Same BK and product order as the
+// large tiles, so every output element is computed identically.
+template <> struct Cfg<PREC_FP32 | kSmall> {
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1;
+    static constexpr int terms = 1, entry_bytes = 32;
+};
+template <> struct Cfg<PREC_BF16X3 | kSmall> {
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1;
+    static constexpr int terms = 2, entry_bytes = 16;
+};
+template <> struct Cfg<PREC_BF16X6 | kSmall> {
+    // two register stages of three terms do not fit two workgroups per CU
+    static constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2;
     static constexpr int terms = 3, entry_bytes = 16;
 };
 
@@ -284,8 +305,8 @@ struct Loader {
         const int k8 = k8_of(uid);
         const int row = row_of(uid, q);
         u32x4 parts[C::terms * (C::entry_bytes / 16)];
-        Split<PREC>::run(v[u][q], parts);
-        if constexpr (PREC == PREC_FP32) {
+        Split<base_prec(PREC)>::run(v[u][q], parts);
+        if constexpr (base_prec(PREC) == PREC_FP32) {
             u32x4 *dst =
                 reinterpret_cast<u32x4 *>(base + entry_off<ROWS, KF, C::entry_bytes>(0, row, k8));
             dst[0] = parts[0];
@@ -312,8 +333,8 @@ struct Loader {
             for (int q = 0; q < R; ++q) {
                 const int row = row_of(uid, q);
                 u32x4 parts[C::terms * (C::entry_bytes / 16)];
-                Split<PREC>::run(v[u][q], parts);
-                if constexpr (PREC == PREC_FP32) {
+                Split<base_prec(PREC)>::run(v[u][q], parts);
+                if constexpr (base_prec(PREC) == PREC_FP32) {
                     u32x4 *dst = reinterpret_cast<u32x4 *>(
                         base + entry_off<ROWS, KF, C::entry_bytes>(0, row, k8));
                     dst[0] = parts[0];
@@ -357,7 +378,7 @@ __device__ __forceinline__ void compute_stage(const char *sA, const char *sB,
     constexpr int FM = G::FM, FN = G::FN, KF = G::KF, EB = C::entry_bytes;
 #pragma unroll
     for (int kk = KK0; kk < KK1; ++kk) {
-        if constexpr (PREC == PREC_FP32) {
+        if constexpr (base_prec(PREC) == PREC_FP32) {
             f32x4 a[FM][2], b[FN][2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -381,7 +402,7 @@ __device__ __forceinline__ void compute_stage(const char *sA, const char *sB,
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
                             a[i][e >> 2][e & 3], b[j][e >> 2][e & 3], acc[i][j], 0, 0, 0);
         } else {
-            using P = Products<PREC>;
+            using P = Products<base_prec(PREC)>;
             constexpr int T = C::terms;
             bf16x8 a[FM][T], b[FN][T];
             // reads in first-use order: for each product, a[0], b[*], a[1..]
@@ -428,7 +449,7 @@ __device__ __forceinline__ void compute_half_interleaved(const char *sA, const c
     using C = Cfg<PREC>;
     using G = Geo<PREC>;
     constexpr int FM = G::FM, FN = G::FN, KF = G::KF, EB = C::entry_bytes;
-    if constexpr (PREC == PREC_FP32) {
+    if constexpr (base_prec(PREC) == PREC_FP32) {
         constexpr int NM = 8 * FM * FN, GS = NM / NG;
         f32x4 a[FM][2], b[FN][2];
 #pragma unroll
@@ -456,7 +477,7 @@ __device__ __forceinline__ void compute_half_interleaved(const char *sA, const c
             }
         }
     } else {
-        using P = Products<PREC>;
+        using P = Products<base_prec(PREC)>;
         constexpr int T = C::terms;
         constexpr int NM = P::n * FM * FN, GS = NM / NG;
         bf16x8 a[FM][T], b[FN][T];
@@ -531,12 +552,11 @@ __device__ __forceinline__ void read_b(bf16x8 (&b)[Geo<PREC>::FN][Cfg<PREC>::ter
 // soon as the first half ends, so the matrix core does not drain between the
 // halves.  The split/writes of the next stage interleave with the second
 // half's MFMAs in NG groups (between(g) after each group).
-template <int NG, typename F>
+template <int PR, int NG, typename F>
 __device__ __forceinline__ void stage_x3_pipe1(const char *sA, const char *sB,
-                                               f32x16 (&acc)[Geo<PREC_BF16X3>::FM][Geo<PREC_BF16X3>::FN],
+                                               f32x16 (&acc)[Geo<PR>::FM][Geo<PR>::FN],
                                                int wm, int wn, int lane, F &&between)
 {
-    constexpr int PR = PREC_BF16X3;
     constexpr int FM = Geo<PR>::FM, FN = Geo<PR>::FN;
     bf16x8 a0[FM][2], b0[FN][2], a1[FM][2], b1[FN][2];
     read_a<PR>(a0, sA, 1, 0, wm, lane);   // lo A
@@ -690,13 +710,14 @@ __device__ __forceinline__ void interleave_hint()
 {
     using G = Geo<PREC>;
     using C = Cfg<PREC>;
-    constexpr int NPROD = PREC == PREC_FP32 ? 8 : PREC == PREC_BF16X3 ? 3 : 6;
+    constexpr int BP = base_prec(PREC);
+    constexpr int NPROD = BP == PREC_FP32 ? 8 : BP == PREC_BF16X3 ? 3 : 6;
     constexpr int NMFMA = G::FM * G::FN * NPROD * NKF;
     constexpr int NREAD = (G::FM + G::FN) * C::terms * (C::entry_bytes / 16) * NKF;
     // LDS writes of one stage: (rows of A + rows of B) x BK / 8 entries per
     // term, spread over the workgroup
     constexpr int NWRITE = (C::BM + C::BN) * (C::BK / 8) * C::terms * (C::entry_bytes / 16) / G::NT;
-    constexpr int VALU_PER = PREC == PREC_FP32 ? 0 : PREC == PREC_BF16X3 ? 4 : 2;
+    constexpr int VALU_PER = BP == PREC_FP32 ? 0 : BP == PREC_BF16X3 ? 4 : 2;
     constexpr int W_EVERY = NMFMA / NWRITE > 0 ? NMFMA / NWRITE : 1;
     __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
 #pragma unroll
@@ -813,7 +834,6 @@ __device__ __forceinline__ void k_loop1(const GemmDesc &d, int64_t row0, int64_t
     using C = Cfg<PREC>;
     using G = Geo<PREC>;
     constexpr int BK = C::BK;
-    static_assert(G::KF == 2, "PIPE 1 splits a stage into two 16-k halves");
     Loader<C::BM, BK, G::NT, AKC> la;
     Loader<C::BN, BK, G::NT, BKC> lb;
     const int64_t nst = (d.K + BK - 1) / BK;
@@ -852,8 +872,14 @@ __device__ __forceinline__ void k_loop1(const GemmDesc &d, int64_t row0, int64_t
                 lb.template store_entry<PREC>(sn + G::a_bytes, (g - EA) / decltype(lb)::R,
                                               (g - EA) % decltype(lb)::R);
         };
-        if constexpr (PREC == PREC_BF16X3) {
-            stage_x3_pipe1<EA + EB_>(sc, sc + G::a_bytes, acc, wm, wn, lane, between);
+        if constexpr (G::KF == 1) {
+            // one 16-k block per stage: compute, then split the next stage
+            compute_stage<PREC>(sc, sc + G::a_bytes, acc, wm, wn, lane);
+            __builtin_amdgcn_sched_barrier(0);
+            la.template store<PREC>(sn);
+            lb.template store<PREC>(sn + G::a_bytes);
+        } else if constexpr (base_prec(PREC) == PREC_BF16X3) {
+            stage_x3_pipe1<PREC, EA + EB_>(sc, sc + G::a_bytes, acc, wm, wn, lane, between);
         } else {
             compute_stage<PREC, 0, 1>(sc, sc + G::a_bytes, acc, wm, wn, lane);
             __builtin_amdgcn_sched_barrier(0);
@@ -886,18 +912,21 @@ __device__ __forceinline__ void k_loop1(const GemmDesc &d, int64_t row0, int64_t
     }
 }
 
-template <int PREC, bool AKC, bool BKC, bool GUARD>
+// GROUPED: the persistent kernel keeps extra state live across tiles; where
+// two register stages would spill there, one stage is used (same arithmetic,
+// same k order, so identical results).
+template <int PREC, bool AKC, bool BKC, bool GUARD, bool GROUPED = false>
 __device__ __forceinline__ void k_loop(const GemmDesc &d, int64_t row0, int64_t col0,
                                        f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
                                        char *smem, int wm, int wn, int lane)
 {
-    if constexpr (Cfg<PREC>::PIPE == 1)
+    if constexpr (Cfg<PREC>::PIPE == 1 || GROUPED)
         k_loop1<PREC, AKC, BKC, GUARD>(d, row0, col0, acc, smem, wm, wn, lane);
     else
         k_loop2<PREC, AKC, BKC, GUARD>(d, row0, col0, acc, smem, wm, wn, lane);
 }
 
-template <int PREC, bool AKC, bool BKC>
+template <int PREC, bool AKC, bool BKC, bool GROUPED = false>
 __device__ __forceinline__ void gemm_tile(const GemmDesc &d, int tm, int tn, char *smem,
                                           double *red)
 {
@@ -916,9 +945,9 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &d, int tm, int tn, cha
 
     const bool interior = row0 + C::BM <= d.M && col0 + C::BN <= d.N && d.vec_a && d.vec_b;
     if (interior)
-        k_loop<PREC, AKC, BKC, false>(d, row0, col0, acc, smem, wm, wn, lane);
+        k_loop<PREC, AKC, BKC, false, GROUPED>(d, row0, col0, acc, smem, wm, wn, lane);
     else
-        k_loop<PREC, AKC, BKC, true>(d, row0, col0, acc, smem, wm, wn, lane);
+        k_loop<PREC, AKC, BKC, true, GROUPED>(d, row0, col0, acc, smem, wm, wn, lane);
     epilogue<PREC>(d, acc, tm, tn, wm, wn, lane, red);
 }
 
@@ -949,7 +978,7 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC)
         const GemmDesc d = probs[gi.prob];
         int tm, tn;
         tile_coords(d, gi.tile, tm, tn);
-        gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
+        gemm_tile<PREC, AKC, BKC, true>(d, tm, tn, smem, red);
         __syncthreads();
     }
 }
@@ -957,10 +986,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC)
 // ---------------------------------------------------------------- launchers
 
 template <int PREC>
-hipError_t launch_t(const GemmDesc &d, hipStream_t s)
+hipError_t launch_one(const GemmDesc &d, hipStream_t s)
 {
-    if (d.num_tiles <= 0)
-        return hipSuccess;
     dim3 grid(d.num_tiles), block(Geo<PREC>::NT);
     if (d.a_kcontig && d.b_kcontig)
         hipLaunchKernelGGL((gemm_kernel<PREC, true, true>), grid, block, 0, s, d);
@@ -974,11 +1001,19 @@ hipError_t launch_t(const GemmDesc &d, hipStream_t s)
 }
 
 template <int PREC>
-hipError_t launch_grouped_t(int akc, int bkc, const GemmDesc *probs, const GroupItem *items,
-                            int num_items, int grid_size, hipStream_t s)
+hipError_t launch_t(const GemmDesc &d, hipStream_t s)
 {
-    if (num_items <= 0)
+    if (d.num_tiles <= 0)
         return hipSuccess;
+    return d.small ? launch_one<PREC | kSmall>(d, s) : launch_one<PREC>(d, s);
+}
+
+// grid_size is the number of CUs; small tiles run two workgroups per CU.
+template <int PREC>
+hipError_t launch_grouped_one(int akc, int bkc, const GemmDesc *probs, const GroupItem *items,
+                              int num_items, int grid_size, hipStream_t s)
+{
+    grid_size *= Cfg<PREC>::OCC;
     dim3 grid(grid_size < num_items ? grid_size : num_items), block(Geo<PREC>::NT);
     if (akc && bkc)
         hipLaunchKernelGGL((gemm_grouped_kernel<PREC, true, true>), grid, block, 0, s, probs,
@@ -993,6 +1028,17 @@ hipError_t launch_grouped_t(int akc, int bkc, const GemmDesc *probs, const Group
         hipLaunchKernelGGL((gemm_grouped_kernel<PREC, false, false>), grid, block, 0, s, probs,
                            items, num_items);
     return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_grouped_t(int akc, int bkc, int small, const GemmDesc *probs,
+                            const GroupItem *items, int num_items, int grid_size, hipStream_t s)
+{
+    if (num_items <= 0)
+        return hipSuccess;
+    return small ? launch_grouped_one<PREC | kSmall>(akc, bkc, probs, items, num_items,
+                                                     grid_size, s)
+                 : launch_grouped_one<PREC>(akc, bkc, probs, items, num_items, grid_size, s);
 }
 
 }  // namespace dev

@@ -159,8 +159,8 @@ static size_t max_update_tiles(const PolarPlan &p)
 {
     size_t t = 0;
     for (int pr : {PREC_FP32, PREC_BF16X3, PREC_BF16X6}) {
-        const size_t tm = (size_t)((p.m + tile_m(pr) - 1) / tile_m(pr));
-        const size_t tn = (size_t)((p.n + tile_n(pr) - 1) / tile_n(pr));
+        const size_t tm = (size_t)((p.m + tile_m(pr, 1) - 1) / tile_m(pr, 1));
+        const size_t tn = (size_t)((p.n + tile_n(pr, 1) - 1) / tile_n(pr, 1));
         t = std::max(t, tm * tn);
     }
     return t;

@@ -42,14 +42,16 @@ struct GemmDesc {
     int vec_a, vec_b;  // operand addresses allow 16-byte vector loads
     int tiles_m, tiles_n;
     int num_tiles;     // tiles launched (upper triangle only for gram)
+    int small;         // 128 x 128 tiles (chosen from the problem's own shape)
 };
 
-// Tile geometry of each precision (fixed, so results never depend on what
-// else is in a launch).
-int tile_m(int prec);
-int tile_n(int prec);
+// Tile geometry of each precision and tile class.  Both tile classes use the
+// same K stages and product order, so the choice (made from the problem's own
+// shape only) never changes a result.
+int tile_m(int prec, int small = 0);
+int tile_n(int prec, int small = 0);
 
-// Fills the derived fields (vec flags, tile counts) of d.
+// Fills the derived fields (tile class, vec flags, tile counts) of d.
 void gemm_finalize(GemmDesc &d, int prec);
 
 hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s);
@@ -60,7 +62,7 @@ struct GroupItem {
     int prob;
     int tile;   // linear tile index within the problem
 };
-hipError_t launch_gemm_grouped(int prec, int a_kcontig, int b_kcontig,
+hipError_t launch_gemm_grouped(int prec, int a_kcontig, int b_kcontig, int small,
                                const GemmDesc *probs_dev,
                                const GroupItem *items_dev, int num_items,
                                int grid_size, hipStream_t s);

@@ -135,8 +135,8 @@ size_t max_tiles(int64_t m, int64_t n)
 {
     size_t t = 0;
     for (int pr : {PREC_FP32, PREC_BF16X3, PREC_BF16X6})
-        t = std::max(t, (size_t)((m + tile_m(pr) - 1) / tile_m(pr)) *
-                            (size_t)((n + tile_n(pr) - 1) / tile_n(pr)));
+        t = std::max(t, (size_t)((m + tile_m(pr, 1) - 1) / tile_m(pr, 1)) *
+                            (size_t)((n + tile_n(pr, 1) - 1) / tile_n(pr, 1)));
     return t;
 }
 
@@ -208,7 +208,7 @@ void carve(Req *r, char *base)
 }
 
 struct Launch {
-    int prec, akc, bkc;
+    int prec, akc, bkc, small;
     std::vector<GemmDesc> probs;
     std::vector<GroupItem> items;
 };
@@ -239,7 +239,7 @@ static hipError_t run_launches(la_server *s, std::vector<Launch> &ls, size_t &dp
             e = hipMemcpyAsync(di, s->h_stage + kDescBytes + ipos, ib, hipMemcpyHostToDevice,
                                s->stream);
         if (e == hipSuccess)
-            e = launch_gemm_grouped(L.prec, L.akc, L.bkc, dd, di, (int)L.items.size(),
+            e = launch_gemm_grouped(L.prec, L.akc, L.bkc, L.small, dd, di, (int)L.items.size(),
                                     s->ctx->num_cus, s->stream);
         if (e != hipSuccess)
             return e;
@@ -253,10 +253,10 @@ static void add_problem(std::vector<Launch> &ls, int prec, int akc, int bkc, con
 {
     Launch *L = nullptr;
     for (auto &x : ls)
-        if (x.prec == prec && x.akc == akc && x.bkc == bkc)
+        if (x.prec == prec && x.akc == akc && x.bkc == bkc && x.small == d.small)
             L = &x;
     if (!L) {
-        ls.push_back(Launch{prec, akc, bkc, {}, {}});
+        ls.push_back(Launch{prec, akc, bkc, d.small, {}, {}});
         L = &ls.back();
     }
     const int pid = (int)L->probs.size();
