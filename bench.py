@@ -108,22 +108,23 @@ def cpu_baseline(A, B, C_gpu, budget_s: float, seed: int = 203):
     }, float(est), tiles
 
 
-def polar_section(la, torch, n=16384, lo=1e-6, seeds=(301, 302, 303)):
-    """Polar factorisation of an n x n A = Q diag(s) V^T (cond 1/lo), AUTO policy
-    (6xBF16 preconditioning, 3xBF16 Newton-Schulz and H) and all-FP32-MFMA."""
+def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
+    """Polar factorisation of an m x n A = Q diag(s) V^T (cond 1/lo), AUTO policy
+    (6xBF16 preconditioning and H, 3xBF16 Newton-Schulz) and all-FP32-MFMA."""
     import la_inputs
 
     t0 = time.perf_counter()
-    A, Q, s, V = la_inputs.polar_case_torch(n, n, lo, seeds)
+    A, Q, s, V = la_inputs.polar_case_torch(m, n, lo, seeds)
     del Q, V
     torch.cuda.empty_cache()
     Ad = torch.from_numpy(A).to("cuda:0")
     U = torch.empty_like(Ad)
-    H = torch.empty_like(Ad)
-    print(f"[bench] polar inputs {n}x{n} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+    H = torch.empty((n, n), dtype=torch.float32, device="cuda:0")
+    print(f"[bench] polar inputs {m}x{n} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
           flush=True)
-    out = {"workload": f"polar {n}x{n} FP32, A = Q diag(s) V^T, Haar Q, V, s log-uniform "
+    out = {"workload": f"polar {m}x{n} FP32, A = Q diag(s) V^T, Haar Q, V, s log-uniform "
                        f"in [{lo:g}, 1], seeds {seeds[0]}/{seeds[1]}/{seeds[2]}"}
+    mn2 = float(m) * float(n) * float(n)
     policies = {"auto": {}, "fp32": dict(prec_precond=1, prec_ns=1, prec_h=1)}
     for name, opts in policies.items():
         la.polar(Ad, U=U, H=H, **opts)          # warm-up (same work)
@@ -133,20 +134,46 @@ def polar_section(la, torch, n=16384, lo=1e-6, seeds=(301, 302, 303)):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         k = info["iters_precond"] + info["iters_ns"]
-        alg = (3.0 * k + 2.0) * float(n) ** 3          # Gram n^3 + update 2n^3 per step, H 2n^3
-        paper_eq = 2.0 * (2 * k + 1) * float(n) ** 3   # "about 50 matmuls" convention
+        alg = (3.0 * k + 2.0) * mn2          # Gram mn^2 + update 2mn^2 per step, H 2mn^2
+        paper_eq = 2.0 * (2 * k + 1) * mn2   # "about 50 matmuls" convention
         out[name] = {"seconds": round(dt, 3), "iters_precond": info["iters_precond"],
                      "iters_ns": info["iters_ns"], "tflops_algorithmic": round(alg / dt / 1e12, 1),
                      "tflops_paper_equivalent": round(paper_eq / dt / 1e12, 1)}
-        print(f"[bench] polar {name}: {dt:.2f} s, {out[name]}", file=sys.stderr, flush=True)
+        print(f"[bench] polar {m}x{n} {name}: {dt:.2f} s, {out[name]}", file=sys.stderr,
+              flush=True)
     out["speedup_auto_vs_fp32"] = round(out["fp32"]["seconds"] / out["auto"]["seconds"], 2)
     return out
 
 
-def serving_section(la, torch, rate=100.0, duration=10.0, pool_size=48, seed=401):
-    """Poisson stream of square polar requests (n log-uniform in [128, 4096],
-    cond 10^U(1,6)) against the continuous-batching server; p50/p99 latency from
-    submit to completed poll."""
+def oracle_polar_timing(sizes=(256, 512, 1024), lo=1e-6, seeds=(103, 104, 105)):
+    """The FP64 oracle polar (same s0 and eps as the FP32 paths, so the same
+    iteration counts) timed on the host at small n; its per-step rate
+    extrapolated by n^3 to the large workloads (labelled extrapolated)."""
+    import la_inputs
+    import oracle
+
+    eps = 2.0 ** -23
+    res = {}
+    for n in sizes:
+        A = la_inputs.polar_case(n, n, lo, seeds).A32.astype(np.float64)
+        t0 = time.perf_counter()
+        _, _, info = oracle.polar(A, s_minus=0.1, s0=eps, eps=eps, max_iter=100)
+        dt = time.perf_counter() - t0
+        k = info.iters_precond + info.iters_ns
+        res[n] = {"seconds": round(dt, 3), "iters": k,
+                  "gflops": round((3.0 * k + 2.0) * n ** 3 / dt / 1e9, 2)}
+        print(f"[bench] oracle polar {n}: {dt:.2f} s, {res[n]}", file=sys.stderr, flush=True)
+    big = max(sizes)
+    rate = res[big]["gflops"] * 1e9
+    return {"kind": "oracle", "cores": oracle.num_threads(), "measured": res,
+            "extrapolated_seconds": {
+                "16384x16384 (28 steps)": round((3.0 * 28 + 2.0) * 16384.0 ** 3 / rate, 0),
+                "131072x4096 (24 steps)": round((3.0 * 24 + 2.0) * 131072.0 * 4096.0 ** 2 / rate, 0)},
+            "note": f"rate of the FP64 oracle at n={big}, scaled by flops; extrapolated, not run"}
+
+
+def serving_pool(torch, pool_size=48, seed=401):
+    """Pool of square polar inputs (n log-uniform in [128, 4096], cond 10^U(1,6))."""
     import la_inputs
 
     t0 = time.perf_counter()
@@ -158,14 +185,22 @@ def serving_section(la, torch, rate=100.0, duration=10.0, pool_size=48, seed=401
                                         seed * 1000 + 3 * i + 2))[0]
             for i, (n, c) in enumerate(zip(sizes, conds))]
     torch.cuda.empty_cache()
-    stream = la_inputs.serve_stream(rate, duration, seed, pool_size)
-    print(f"[bench] serving pool of {pool_size} in {time.perf_counter() - t0:.1f} s, "
-          f"{len(stream)} arrivals", file=sys.stderr, flush=True)
+    print(f"[bench] serving pool of {pool_size} in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    return pool
+
+
+def serving_section(la, pool, rate=100.0, duration=10.0, seed=401, exclude_s=1.0):
+    """Poisson stream of requests from the pool against the continuous-batching
+    server; p50/p99 latency from submit to completed poll, over the requests
+    submitted after the first exclude_s seconds (warm-up of the queue)."""
+    import la_inputs
+
+    stream = la_inputs.serve_stream(rate, duration, seed, len(pool))
     lat = []
     flops = 0.0
     with la.Server(16 << 30, max_slots=64) as srv:
-        # warm-up: one request of each size class compiles nothing but touches the code
-        w = srv.submit(pool[0])
+        w = srv.submit(pool[0])            # touch the code paths once
         while srv.poll(w) is None:
             time.sleep(0.001)
         pending = {}
@@ -175,30 +210,59 @@ def serving_section(la, torch, rate=100.0, duration=10.0, pool_size=48, seed=401
             now = time.perf_counter() - start
             while i < len(stream) and stream[i][0] <= now:
                 A = pool[stream[i][1]]
+                t_sub = time.perf_counter()
                 rid = srv.submit(A)
-                pending[rid] = (time.perf_counter(), A.shape[0])
+                pending[rid] = (t_sub, A.shape[0], stream[i][0] >= exclude_s)
                 i += 1
             for rid in list(pending):
                 r = srv.poll(rid, want_h=False)
                 if r is not None:
-                    t_sub, n = pending.pop(rid)
-                    lat.append(time.perf_counter() - t_sub)
+                    t_sub, n, counted = pending.pop(rid)
+                    if counted:
+                        lat.append(time.perf_counter() - t_sub)
                     k = r[3]["iters_precond"] + r[3]["iters_ns"]
                     flops += (3.0 * k + 2.0) * float(n) ** 3
             time.sleep(0.0002)
         wall = time.perf_counter() - start
         st = srv.stats()
     lat_ms = np.array(lat) * 1e3
-    return {"workload": f"Poisson arrivals at {rate:g} req/s for {duration:g} s, square n "
-                        f"log-uniform in [128, 4096] (x64), cond 10^U(1,6), pool of {pool_size} "
-                        f"(seed {seed}), AUTO policy",
-            "requests": int(len(lat)), "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
-            "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
-            "mean_ms": round(float(lat_ms.mean()), 2),
-            "throughput_req_s": round(len(lat) / wall, 1),
-            "tflops_algorithmic": round(flops / wall / 1e12, 2),
-            "ticks": int(st["ticks"]), "gpu_busy_frac": round(st["busy_seconds"] / wall, 3),
-            "arena_high_water_gib": round(st["arena_high_water"] / 2 ** 30, 2)}
+    out = {"workload": f"Poisson arrivals at {rate:g} req/s for {duration:g} s, square n "
+                       f"log-uniform in [128, 4096] (x64), cond 10^U(1,6), pool of {len(pool)} "
+                       f"(seed {seed}), AUTO policy; latency over arrivals after {exclude_s:g} s",
+           "requests": int(len(stream)), "latency_samples": int(len(lat)),
+           "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
+           "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
+           "mean_ms": round(float(lat_ms.mean()), 2),
+           "throughput_req_s": round(len(stream) / wall, 1),
+           "tflops_algorithmic": round(flops / wall / 1e12, 2),
+           "ticks": int(st["ticks"]), "gpu_busy_frac": round(st["busy_seconds"] / wall, 3),
+           "arena_high_water_gib": round(st["arena_high_water"] / 2 ** 30, 2)}
+    print(f"[bench] serving {rate:g} req/s: {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def serving_saturation(la, pool, count=160, seed=402):
+    """All `count` requests submitted at once: completion throughput."""
+    g = np.random.default_rng(seed)
+    idx = g.integers(0, len(pool), size=count)
+    flops = 0.0
+    with la.Server(16 << 30, max_slots=64) as srv:
+        start = time.perf_counter()
+        pending = {srv.submit(pool[int(j)]): pool[int(j)].shape[0] for j in idx}
+        while pending:
+            for rid in list(pending):
+                r = srv.poll(rid, want_h=False)
+                if r is not None:
+                    n = pending.pop(rid)
+                    k = r[3]["iters_precond"] + r[3]["iters_ns"]
+                    flops += (3.0 * k + 2.0) * float(n) ** 3
+            time.sleep(0.0005)
+        wall = time.perf_counter() - start
+    out = {"requests": count, "seconds": round(wall, 2),
+           "throughput_req_s": round(count / wall, 1),
+           "tflops_algorithmic": round(flops / wall / 1e12, 1)}
+    print(f"[bench] serving saturation: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -210,6 +274,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-polar", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving stream (for profiling the grouped kernels)")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="also run the serving stream at 25/50/150/200 req/s and a saturation "
+                         "burst (about 1.5 minutes more)")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="length of the Poisson stream")
+    ap.add_argument("--no-tall", action="store_true", help="skip the 131072 x 4096 polar")
+    ap.add_argument("--no-oracle-polar", action="store_true")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -235,6 +308,12 @@ def main():
 
     import la_inputs
     import paper_2112_09017_amd as la
+
+    if args.serving_only:
+        pool = serving_pool(torch)
+        print(json.dumps({"serving": serving_section(la, pool, duration=args.serving_seconds)}),
+              flush=True)
+        return
 
     dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
@@ -312,8 +391,19 @@ def main():
     if not args.no_polar and args.only is None:
         out["polar"] = polar_section(la, torch)
         torch.cuda.empty_cache()
+        if not args.no_tall:
+            out["polar_tall"] = polar_section(la, torch, 131072, 4096, 1e-4, (501, 502, 503))
+            torch.cuda.empty_cache()
+        if not args.no_oracle_polar:
+            out["polar"]["cpu_oracle"] = oracle_polar_timing()
     if not args.no_serving and args.only is None:
-        out["serving"] = serving_section(la, torch)
+        pool = serving_pool(torch)
+        out["serving"] = serving_section(la, pool, duration=args.serving_seconds)
+        if args.serving_sweep:
+            out["serving_sweep"] = {f"{r:g}": serving_section(la, pool, rate=r,
+                                                              duration=args.serving_seconds)
+                                    for r in (25.0, 50.0, 150.0, 200.0)}
+            out["serving_saturation"] = serving_saturation(la, pool)
     print(json.dumps(out), flush=True)
 
 

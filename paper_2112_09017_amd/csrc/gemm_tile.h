@@ -44,12 +44,6 @@ constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------- configs
 
-#ifndef LA_X3_WM
-#define LA_X3_WM 2
-#endif
-#ifndef LA_X3_WN
-#define LA_X3_WN 2
-#endif
 // A kernel's PREC template argument is the arithmetic (PREC_FP32 / _BF16X3 /
 // _BF16X6) plus kSmall for the 128 x 128 tile variant.
 constexpr int kSmall = 16;
@@ -60,31 +54,33 @@ template <int PREC> struct Cfg;
 // the second 16-k half of the current stage.  PIPE 2: two register stages,
 // BK = 16, the split of stage s+1 runs under the MFMAs of stage s.
 template <> struct Cfg<PREC_FP32> {
-    static constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 2, OCC = 1, PIPE = 1;
+    static constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 2, OCC = 1, PIPE = 1, GOCC = 1;
     static constexpr int terms = 1, entry_bytes = 32;
 };
 template <> struct Cfg<PREC_BF16X3> {
-    static constexpr int BM = 256, BN = 256, BK = 32, WM = LA_X3_WM, WN = LA_X3_WN, OCC = 1, PIPE = 1;
+    static constexpr int BM = 256, BN = 256, BK = 32, WM = 2, WN = 2, OCC = 1, PIPE = 1, GOCC = 1;
     static constexpr int terms = 2, entry_bytes = 16;
 };
 template <> struct Cfg<PREC_BF16X6> {
-    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2;
+    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2, GOCC = 1;
     static constexpr int terms = 3, entry_bytes = 16;
 };
 // 128 x 128 tiles (64 x 64 per wave), two workgroups per CU: problems too
 // small to give every CU a 256 x 256 tile.  Same BK and product order as the
 // large tiles, so every output element is computed identically.
 template <> struct Cfg<PREC_FP32 | kSmall> {
-    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1;
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1, GOCC = 2;
     static constexpr int terms = 1, entry_bytes = 32;
 };
 template <> struct Cfg<PREC_BF16X3 | kSmall> {
-    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1;
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 2, WN = 2, OCC = 2, PIPE = 1, GOCC = 2;
     static constexpr int terms = 2, entry_bytes = 16;
 };
 template <> struct Cfg<PREC_BF16X6 | kSmall> {
-    // two register stages of three terms do not fit two workgroups per CU
-    static constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2;
+    // two register stages of three terms do not fit two workgroups per CU.  The
+    // grouped kernel (one register stage) runs two per CU: its work-lists are
+    // long enough that the other workgroup's MFMAs cover this one's split.
+    static constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2, GOCC = 2;
     static constexpr int terms = 3, entry_bytes = 16;
 };
 
@@ -191,14 +187,10 @@ __device__ __forceinline__ int frag_off(int t, int frow, int fk, int lane)
 // tail use load_guarded.
 template <int ROWS, int BK, int NT, bool KC>
 struct Loader {
-    // k-contiguous operands take up to 4 rows per unit; row-contiguous ones one
-    // row per lane, so that 16 consecutive lanes always write 16 consecutive
-    // fragment slots
-#ifndef LA_RC_ROWS
-#define LA_RC_ROWS 4
-#endif
-    static constexpr int RMAX = (ROWS * BK / (8 * NT) >= 4) ? 4 : (ROWS * BK / (8 * NT) >= 2) ? 2 : 1;
-    static constexpr int R = !KC ? (LA_RC_ROWS < RMAX ? LA_RC_ROWS : RMAX) : RMAX;
+    // up to 4 rows per unit, fewer when the stage is too small to give every
+    // thread 4; the row map below keeps 16 consecutive lanes writing 16
+    // consecutive fragment slots
+    static constexpr int R = (ROWS * BK / (8 * NT) >= 4) ? 4 : (ROWS * BK / (8 * NT) >= 2) ? 2 : 1;
     static constexpr int NK8 = BK / 8;
     static constexpr int UNITS = ROWS * BK / (8 * R);
     static constexpr int UPT = (UNITS + NT - 1) / NT;
@@ -967,7 +959,7 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
 // Persistent grouped kernel: workgroup b runs items b, b + grid, ...; each
 // item is one tile of one problem, computed exactly as gemm_kernel would.
 template <int PREC, bool AKC, bool BKC>
-__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC)
+__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
     gemm_grouped_kernel(const GemmDesc *__restrict__ probs, const GroupItem *__restrict__ items,
                         int num_items)
 {
@@ -1013,7 +1005,7 @@ template <int PREC>
 hipError_t launch_grouped_one(int akc, int bkc, const GemmDesc *probs, const GroupItem *items,
                               int num_items, int grid_size, hipStream_t s)
 {
-    grid_size *= Cfg<PREC>::OCC;
+    grid_size *= Cfg<PREC>::GOCC;
     dim3 grid(grid_size < num_items ? grid_size : num_items), block(Geo<PREC>::NT);
     if (akc && bkc)
         hipLaunchKernelGGL((gemm_grouped_kernel<PREC, true, true>), grid, block, 0, s, probs,

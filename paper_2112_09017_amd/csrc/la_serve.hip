@@ -115,8 +115,9 @@ struct Req {
     PolarPlan plan;
     State state = QUEUED;
     la_status status = LA_OK;
-    float *a_pinned = nullptr;  // input, then released after upload
-    float *u_pinned = nullptr;
+    // pinned host staging: the input A, reused for the result U (both m x n;
+    // the upload has completed before U is copied back), and H
+    float *io_pinned = nullptr;
     float *h_pinned = nullptr;
     // device state, carved from the arena block
     size_t off = 0, bytes = 0;
@@ -291,8 +292,8 @@ void la_server::tick()
     // 1. newly admitted: upload, ||A||_F in FP64
     for (Req *r : fresh) {
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r->A, r->a_pinned, (size_t)r->m * r->n * 4, hipMemcpyHostToDevice,
-                               stream);
+            e = hipMemcpyAsync(r->A, r->io_pinned, (size_t)r->m * r->n * 4,
+                               hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = launch_sumsq(r->A, r->m, r->n, r->n, r->sumsq, stream);
         if (e == hipSuccess)
@@ -304,8 +305,6 @@ void la_server::tick()
         e = hipStreamSynchronize(stream);
     for (size_t i = 0; i < fresh.size() && e == hipSuccess; ++i) {
         Req *r = fresh[i];
-        hipHostFree(r->a_pinned);
-        r->a_pinned = nullptr;
         const double fro = sqrt(h_deltas[i]);
         r->info.fro_norm_a = fro;
         if (!(fro > 0.0) || !isfinite(fro)) {
@@ -473,7 +472,7 @@ void la_server::tick()
                 continue;
             e2 = launch_symmetrize(r->P, r->n, r->n, stream);
             if (e2 == hipSuccess)
-                e2 = hipMemcpyAsync(r->u_pinned, r->X[r->cur], (size_t)r->m * r->n * 4,
+                e2 = hipMemcpyAsync(r->io_pinned, r->X[r->cur], (size_t)r->m * r->n * 4,
                                     hipMemcpyDeviceToHost, stream);
             if (e2 == hipSuccess && r->h_pinned)
                 e2 = hipMemcpyAsync(r->h_pinned, r->P, (size_t)r->n * r->n * 4,
@@ -619,19 +618,16 @@ la_status la_serve_submit(la_server *s, int64_t m, int64_t n, const float *A_hos
     r->info.last_delta = INFINITY;
     r->info.stop_reason = 2;
     const size_t mn = (size_t)m * n;
-    hipError_t e = hipHostMalloc((void **)&r->a_pinned, mn * 4, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&r->u_pinned, mn * 4, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&r->io_pinned, mn * 4, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&r->h_pinned, (size_t)n * n * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
-        if (r->a_pinned) hipHostFree(r->a_pinned);
-        if (r->u_pinned) hipHostFree(r->u_pinned);
+        if (r->io_pinned) hipHostFree(r->io_pinned);
         set_error("la_serve_submit: pinned allocation failed: %s", hipGetErrorString(e));
         return LA_ERR_OUT_OF_MEMORY;
     }
     for (int64_t i = 0; i < m; ++i)
-        memcpy(r->a_pinned + i * n, A_host + i * lda, (size_t)n * 4);
+        memcpy(r->io_pinned + i * n, A_host + i * lda, (size_t)n * 4);
     r->t_submit = now_s();
     std::lock_guard<std::mutex> g(s->mu);
     r->id = s->next_id++;
@@ -665,15 +661,14 @@ la_status la_serve_poll(la_server *s, uint64_t id, float *U_host, float *H_host,
         s->all.erase(it);
     }
     if (U_host && (r->status == LA_OK || r->status == LA_ERR_NOT_CONVERGED))
-        memcpy(U_host, r->u_pinned, (size_t)r->m * r->n * 4);
+        memcpy(U_host, r->io_pinned, (size_t)r->m * r->n * 4);
     if (H_host && (r->status == LA_OK || r->status == LA_ERR_NOT_CONVERGED))
         memcpy(H_host, r->h_pinned, (size_t)r->n * r->n * 4);
     if (info)
         *info = r->info;
     if (req_status)
         *req_status = r->status;
-    if (r->a_pinned) hipHostFree(r->a_pinned);
-    if (r->u_pinned) hipHostFree(r->u_pinned);
+    if (r->io_pinned) hipHostFree(r->io_pinned);
     if (r->h_pinned) hipHostFree(r->h_pinned);
     return LA_OK;
 }
@@ -703,8 +698,7 @@ la_status la_serve_destroy(la_server *s)
     hipStreamSynchronize(s->stream);
     for (auto &kv : s->all) {
         Req *r = kv.second.get();
-        if (r->a_pinned) hipHostFree(r->a_pinned);
-        if (r->u_pinned) hipHostFree(r->u_pinned);
+        if (r->io_pinned) hipHostFree(r->io_pinned);
         if (r->h_pinned) hipHostFree(r->h_pinned);
     }
     hipStreamDestroy(s->stream);
