@@ -8,6 +8,8 @@ GPU library computes, written from the paper (arXiv 2112.09017):
                    (RogueMatrix) and (NewtonSchulz), section III.D;
 * ``polar_2x2`` -- the closed-form polar factor of a 2 x 2 matrix
                    (eqs. PolarDecomp, SVDdef);
+* ``inverse``   -- Algorithm NS_Inverse (Newton-Schulz inversion), with its
+                   scalar step ``inv_map``;
 * scalar maps   -- eqs. (NS_scalar), (a_def), (RogueScalar) and the
                    preconditioning step count of Algorithm NS_Polar.
 
@@ -51,6 +53,25 @@ class PolarInfo:
 _REASONS = {0: "tol", 1: "stagnation", 2: "cap"}
 
 
+class _InvInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("stop_reason", ctypes.c_int),
+        ("gram_norm", ctypes.c_double),
+        ("last_delta", ctypes.c_double),
+        ("last_tol", ctypes.c_double),
+    ]
+
+
+@dataclass
+class InverseInfo:
+    iters: int
+    stop_reason: str
+    gram_norm: float
+    last_delta: float
+    last_tol: float
+
+
 def _bind(path: str):
     lib = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -74,6 +95,11 @@ def _bind(path: str):
     lib.orc_polar.restype = ctypes.c_int
     lib.orc_polar_2x2.argtypes = [dp, dp, dp]
     lib.orc_polar_2x2.restype = ctypes.c_int
+    lib.orc_inv_map.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.orc_inv_map.restype = ctypes.c_double
+    lib.orc_inverse.argtypes = [i64, i64, dp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                dp, i64, ctypes.c_void_p]
+    lib.orc_inverse.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     return lib
@@ -177,6 +203,28 @@ class Oracle:
         """OpenMP threads the oracle's GEMM uses."""
         return int(self._lib.orc_num_threads())
 
+    def inv_map(self, d: float, x: float) -> float:
+        """One Newton-Schulz inversion step on a scalar: x (2 - d x)."""
+        return float(self._lib.orc_inv_map(d, x))
+
+    def inverse(self, A, u: float = 2.0 ** -53, normalize: bool = True, max_iter: int = 200):
+        """Algorithm NS_Inverse in FP64.  A is n x m; returns (X (m x n), InverseInfo).
+        X A = I for n >= m, A X = I for n <= m.  ``u`` is the starting tolerance
+        (the unit roundoff of the precision being emulated); ``normalize``
+        measures the step on A / sqrt(||A A^T||_F) (see la_oracle.c)."""
+        A = _f64(A)
+        n, m = A.shape
+        X = np.zeros((m, n), np.float64)
+        info = _InvInfo()
+        rc = self._lib.orc_inverse(n, m, _ptr(A), m, u, int(normalize), max_iter, _ptr(X), n,
+                                   ctypes.byref(info))
+        if rc == -2:
+            raise FloatingPointError("||A A^T||_F is zero or not finite")
+        if rc != 0:
+            raise ValueError("orc_inverse: bad arguments or allocation failure")
+        return X, InverseInfo(info.iters, _REASONS.get(info.stop_reason, "?"), info.gram_norm,
+                              info.last_delta, info.last_tol)
+
     def polar_2x2(self, A):
         """Closed-form polar factors (U, H) of a full-rank 2 x 2 matrix."""
         A = _f64(A).reshape(2, 2)
@@ -217,6 +265,14 @@ def polar(*a, **k):
 
 def polar_2x2(*a, **k):
     return _load().polar_2x2(*a, **k)
+
+
+def inv_map(*a, **k):
+    return _load().inv_map(*a, **k)
+
+
+def inverse(*a, **k):
+    return _load().inverse(*a, **k)
 
 
 def num_threads():

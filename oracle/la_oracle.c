@@ -291,3 +291,106 @@ int orc_polar_2x2(const double *A, double *U, double *H)
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Newton-Schulz matrix inversion (Algorithm NS_Inverse, section III.D).    */
+/* ------------------------------------------------------------------------ */
+
+/* The scalar form of one step on a singular value d: x <- x (2 - d x).  For
+ * a diagonal A every diagonal entry of X follows it independently. */
+double orc_inv_map(double d, double x) { return x * (2.0 - d * x); }
+
+typedef struct {
+    int iters;
+    int stop_reason;      /* 0 tolerance, 2 iteration cap */
+    double gram_norm;     /* a = ||A A^T||_F */
+    double last_delta;    /* delta of the last step (as compared) */
+    double last_tol;      /* the tolerance it was compared with */
+} orc_inverse_info;
+
+/*
+ * A is n x m (row-major, lda >= m) of full rank; X (m x n, ldx >= n)
+ * receives X with X A = I (n >= m) or A X = I (n <= m):
+ *   a <- ||A A^T||_F;  X <- A^T / a;  eps <- u;  delta <- 2 eps
+ *   while delta > eps:  X' <- X (2 I - A X);  delta <- ||X' - X||_F
+ *                       eps <- 2 eps;  X <- X'
+ * X (2 I - A X) is the step for both shapes (it equals (2 I - X A) X); the
+ * second form printed for A X = I only has matching dimensions when A is
+ * square.
+ * Reading where the algorithm is silent: the tolerance is absolute, so it
+ * presumes X at unit scale.  With normalize != 0, delta is measured on the
+ * normalised problem A / sqrt(a) (whose inverse is sqrt(a) X):
+ * delta = sqrt(a) ||X' - X||_F, which makes the stop independent of the
+ * scale of A and equal to the printed test whenever ||A A^T||_F = 1.
+ * normalize == 0 compares ||X' - X||_F as printed.  The loop also stops
+ * after max_iter steps.
+ *
+ * Returns 0, -1 on bad arguments or allocation failure, -2 if a is zero or
+ * not finite.
+ */
+int orc_inverse(int64_t n, int64_t m, const double *A, int64_t lda, double u,
+                int normalize, int max_iter, double *X, int64_t ldx,
+                orc_inverse_info *info)
+{
+    if (n < 1 || m < 1 || lda < m || ldx < n || !(u > 0.0))
+        return -1;
+    orc_inverse_info loc;
+    memset(&loc, 0, sizeof loc);
+
+    double *G = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *T = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *Xc = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *Xn = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    if (!G || !T || !Xc || !Xn) {
+        free(G); free(T); free(Xc); free(Xn);
+        return -1;
+    }
+
+    /* a <- ||A A^T||_F */
+    orc_gemm(0, 1, n, n, m, 1.0, A, lda, A, lda, 0.0, G, n);
+    double a = orc_fro(n, n, G, n);
+    loc.gram_norm = a;
+    if (!(a > 0.0) || !isfinite(a)) {
+        free(G); free(T); free(Xc); free(Xn);
+        if (info) *info = loc;
+        return -2;
+    }
+    /* X <- A^T / a */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            Xc[i * n + j] = A[j * lda + i] / a;
+
+    const double scale = normalize ? sqrt(a) : 1.0;
+    double eps = u;
+    double delta = 2.0 * eps;
+    loc.stop_reason = 0;
+    while (delta > eps) {
+        if (loc.iters >= max_iter) {
+            loc.stop_reason = 2;
+            break;
+        }
+        /* T = 2 I - A X  (n x n) */
+        orc_gemm(0, 0, n, n, m, 1.0, A, lda, Xc, n, 0.0, G, n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                T[i * n + j] = (i == j ? 2.0 : 0.0) - G[i * n + j];
+        /* X' = X T */
+        orc_gemm(0, 0, m, n, n, 1.0, Xc, n, T, n, 0.0, Xn, n);
+        double d2 = 0.0;
+        for (int64_t i = 0; i < m * n; ++i)
+            d2 += (Xn[i] - Xc[i]) * (Xn[i] - Xc[i]);
+        delta = scale * sqrt(d2);
+        eps = 2.0 * eps;
+        double *t = Xc; Xc = Xn; Xn = t;
+        loc.iters++;
+    }
+    loc.last_delta = delta;
+    loc.last_tol = eps;
+
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            X[i * ldx + j] = Xc[i * n + j];
+    free(G); free(T); free(Xc); free(Xn);
+    if (info) *info = loc;
+    return 0;
+}

@@ -288,6 +288,109 @@ def pin_polar_rank_deficient(orc):
     assert np.max(np.abs(U - Q[:, :r] @ V[:, :r].T)) < 1e-11
 
 
+# --------------------------------------------------------------------------- inversion
+
+def _inv_closed_form_iterate(d, a, k):
+    """Algorithm NS_Inverse on a diagonal A = diag(d): with r = d x the residual
+    e = 1 - r squares at every step (1 - r(2 - r) = (1 - r)^2), and X_0 = A^T / a
+    gives e_0 = 1 - d^2 / a, so after k steps x = (1 - e_0^(2^k)) / d."""
+    e0 = 1.0 - d * d / a
+    return (1.0 - e0 ** (2 ** k)) / d
+
+
+def pin_inverse_2x2_golden(orc):
+    g = _golden("inverse_2x2.json")
+    for case in g["cases"]:
+        A = np.array(case["A"], np.float64)
+        X, info = orc.inverse(A)
+        want = np.array(case["inv_times_det"], np.float64) / case["det"]
+        assert info.stop_reason == "tol"
+        assert np.max(np.abs(X - want)) < 1e-13, (case, X)
+
+
+def pin_inverse_vs_numpy(orc):
+    """Square: numpy.linalg.inv; tall / wide: numpy.linalg.pinv, and the
+    one-sided identity the algorithm promises (X A = I or A X = I)."""
+    c = la_inputs.polar_case(48, 48, 1e-2, seeds=(120, 121, 122))
+    A = c.A32.astype(np.float64)
+    X, _ = orc.inverse(A)
+    ref = np.linalg.inv(A)
+    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+    T = la_inputs.gaussian((72, 40), 123).astype(np.float64)
+    Xt, _ = orc.inverse(T)
+    assert Xt.shape == (40, 72)
+    assert np.max(np.abs(Xt @ T - np.eye(40))) < 1e-12
+    assert np.linalg.norm(Xt - np.linalg.pinv(T)) / np.linalg.norm(Xt) < 1e-12
+    W = la_inputs.gaussian((40, 72), 124).astype(np.float64)
+    Xw, _ = orc.inverse(W)
+    assert Xw.shape == (72, 40)
+    assert np.max(np.abs(W @ Xw - np.eye(40))) < 1e-12
+    assert np.linalg.norm(Xw - np.linalg.pinv(W)) / np.linalg.norm(Xw) < 1e-12
+
+
+def pin_inverse_diagonal_closed_form(orc):
+    """Every iterate of a diagonal input, from the closed form of the residual."""
+    d = np.array([1.0, 0.5, 0.25, 3.0, 0.01, 1.5])
+    A = np.diag(d)
+    a = math.sqrt(float(np.sum(d ** 4)))          # ||A A^T||_F
+    for k in range(0, 7):
+        X, info = orc.inverse(A, max_iter=k)
+        assert info.iters == k
+        assert abs(info.gram_norm - a) <= 1e-15 * a
+        want = np.diag(_inv_closed_form_iterate(d, a, k))
+        assert np.max(np.abs(X - want) / np.abs(1.0 / d)[None, :].max()) < 1e-14, k
+    X, info = orc.inverse(A)
+    assert np.max(np.abs(X * d[:, None] - np.eye(len(d)))) < 1e-13
+    # the scalar step squares the residual and has 1/d as its fixed point
+    for dd, x in ((0.5, 0.3), (2.0, 0.1), (1e-3, 7.0), (3.0, 1.0 / 3.0)):
+        y = orc.inv_map(dd, x)
+        assert abs((1.0 - dd * y) - (1.0 - dd * x) ** 2) < 1e-15
+    assert orc.inv_map(4.0, 0.25) == 0.25
+
+
+def pin_inverse_orthogonal_stop_rule(orc):
+    """A = Q orthogonal: A A^T = I, a = sqrt(n), X_k = Q^T (1 - e0^(2^k)) with
+    e0 = 1 - 1/sqrt(n).  The step norm is then known in closed form, so the
+    stopping step of the growing tolerance (eps_k = u 2^k, compared after the
+    k-th step) is fixed; both readings of delta are checked."""
+    n = 16
+    Q = la_inputs.haar(n, 125)
+    a = math.sqrt(n)
+    e0 = 1.0 - 1.0 / a
+    for u in (2.0 ** -24, 2.0 ** -40):
+        for normalize in (True, False):
+            scale = math.sqrt(a) if normalize else 1.0
+            k, eps = 0, u
+            while True:
+                k += 1
+                delta = scale * math.sqrt(n) * (e0 ** (2 ** (k - 1)) - e0 ** (2 ** k))
+                eps *= 2.0
+                if not delta > eps:
+                    break
+            X, info = orc.inverse(Q, u=u, normalize=normalize)
+            assert info.iters == k, (u, normalize, info.iters, k)
+            assert abs(info.last_tol - u * 2.0 ** k) == 0.0
+            assert np.max(np.abs(X - Q.T * (1.0 - e0 ** (2 ** k)))) < 1e-14
+
+
+def pin_inverse_scale_invariance(orc):
+    """With the step measured on the normalised problem, A -> 2^k A gives
+    X -> 2^-k X bitwise and the same step count; at ||A A^T||_F = 1 the two
+    readings of the stop test coincide."""
+    A = la_inputs.polar_case(24, 24, 1e-2, seeds=(126, 127, 128)).A32.astype(np.float64)
+    X, info = orc.inverse(A, u=2.0 ** -24)
+    for k in (-6, 4):
+        Xk, ik = orc.inverse(A * 2.0 ** k, u=2.0 ** -24)
+        assert ik.iters == info.iters
+        assert np.array_equal(Xk, X * 2.0 ** -k)
+    Q = la_inputs.haar(16, 129) * 0.5          # ||Q Q^T / 4||_F = 4 / 4 = 1 exactly
+    X1, i1 = orc.inverse(Q, u=2.0 ** -24, normalize=True)
+    X2, i2 = orc.inverse(Q, u=2.0 ** -24, normalize=False)
+    assert i1.gram_norm == 1.0 or abs(i1.gram_norm - 1.0) < 1e-15
+    assert i1.iters == i2.iters
+    assert np.max(np.abs(X1 - X2)) < 1e-15
+
+
 ALL_PINS = [
     pin_paper_iteration_counts,
     pin_scalar_map_properties,
@@ -303,4 +406,9 @@ ALL_PINS = [
     pin_polar_special_cases,
     pin_polar_scale_invariance,
     pin_polar_rank_deficient,
+    pin_inverse_2x2_golden,
+    pin_inverse_vs_numpy,
+    pin_inverse_diagonal_closed_form,
+    pin_inverse_orthogonal_stop_rule,
+    pin_inverse_scale_invariance,
 ]

@@ -34,6 +34,14 @@ MUTANTS = {
     "closed_form_sign": ("u10 = (c - b) / r; u11 = (a + d) / r;", "u10 = (b - c) / r; u11 = (a + d) / r;"),
     "scalar_map_const": ("return 0.5 * x * (3.0 - x * x);", "return 0.5 * x * (3.0 - 0.9 * x * x);"),
     "precond_steps_off_by_one": ("    while (s < s_minus && count < 10000) {", "    while (s <= 2 * s_minus && count < 10000) {"),
+    "inv_step_constant": ("T[i * n + j] = (i == j ? 2.0 : 0.0) - G[i * n + j];",
+                          "T[i * n + j] = (i == j ? 1.9 : 0.0) - G[i * n + j];"),
+    "inv_x0_scale": ("Xc[i * n + j] = A[j * lda + i] / a;", "Xc[i * n + j] = A[j * lda + i] / sqrt(a);"),
+    "inv_fro_of_a": ("double a = orc_fro(n, n, G, n);", "double a = orc_fro(n, m, A, lda);"),
+    "inv_eps_fixed": ("eps = 2.0 * eps;\n        double *t = Xc;", "eps = 1.0 * eps;\n        double *t = Xc;"),
+    "inv_delta_literal": ("const double scale = normalize ? sqrt(a) : 1.0;", "const double scale = 1.0;"),
+    "inv_delta_sign": ("d2 += (Xn[i] - Xc[i]) * (Xn[i] - Xc[i]);", "d2 += (Xn[i] + Xc[i]) * (Xn[i] + Xc[i]);"),
+    "inv_map_sign": ("return x * (2.0 - d * x);", "return x * (2.0 + d * x);"),
 }
 
 
