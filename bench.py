@@ -172,6 +172,43 @@ def oracle_polar_timing(sizes=(256, 512, 1024), lo=1e-6, seeds=(103, 104, 105)):
             "note": f"rate of the FP64 oracle at n={big}, scaled by flops; extrapolated, not run"}
 
 
+def inverse_section(la, torch, n=16384, lo=1e-2, seeds=(601, 602, 603)):
+    """Newton-Schulz inversion of an n x n A = Q diag(s) V^T (cond 1/lo), AUTO
+    (3xBF16 steps + one 6xBF16 step) and all-FP32-MFMA."""
+    import la_inputs
+
+    t0 = time.perf_counter()
+    A, Q, s, V = la_inputs.polar_case_torch(n, n, lo, seeds)
+    del Q, V
+    torch.cuda.empty_cache()
+    Ad = torch.from_numpy(A).to("cuda:0")
+    X = torch.empty_like(Ad)
+    print(f"[bench] inverse inputs {n}x{n} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    out = {"workload": f"Newton-Schulz inverse {n}x{n} FP32, A = Q diag(s) V^T, Haar Q, V, "
+                       f"s log-uniform in [{lo:g}, 1], seeds {seeds[0]}/{seeds[1]}/{seeds[2]}"}
+    for name, opts in (("auto", {}), ("fp32", dict(prec=1))):
+        la.inverse(Ad, X=X, **opts)          # warm-up (same work)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = la.inverse(Ad, X=X, **opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        k = info["iters"]
+        alg = (4.0 * k + 1.0) * float(n) ** 3     # two 2n^3 products per step, Gram n^3
+        g = torch.randn((n, 16), dtype=torch.float64, device="cuda:0",
+                        generator=torch.Generator(device="cuda:0").manual_seed(604))
+        y = Ad.double() @ (X.double() @ g) - g          # residual probes (check only)
+        res = float(torch.sqrt((y * y).sum() / 16)) / n ** 0.5
+        out[name] = {"seconds": round(dt, 3), "iters": k,
+                     "tflops_algorithmic": round(alg / dt / 1e12, 1),
+                     "residual_probe": float(f"{res:.3g}")}
+        print(f"[bench] inverse {name}: {dt:.2f} s, {out[name]}", file=sys.stderr, flush=True)
+        del y, g
+    out["speedup_auto_vs_fp32"] = round(out["fp32"]["seconds"] / out["auto"]["seconds"], 2)
+    return out
+
+
 def serving_pool(torch, pool_size=48, seed=401):
     """Pool of square polar inputs (n log-uniform in [128, 4096], cond 10^U(1,6))."""
     import la_inputs
@@ -283,6 +320,7 @@ def main():
                     help="length of the Poisson stream")
     ap.add_argument("--no-tall", action="store_true", help="skip the 131072 x 4096 polar")
     ap.add_argument("--no-oracle-polar", action="store_true")
+    ap.add_argument("--no-inverse", action="store_true")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -396,6 +434,9 @@ def main():
             torch.cuda.empty_cache()
         if not args.no_oracle_polar:
             out["polar"]["cpu_oracle"] = oracle_polar_timing()
+    if not args.no_inverse and args.only is None:
+        out["inverse"] = inverse_section(la, torch)
+        torch.cuda.empty_cache()
     if not args.no_serving and args.only is None:
         pool = serving_pool(torch)
         out["serving"] = serving_section(la, pool, duration=args.serving_seconds)

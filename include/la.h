@@ -11,15 +11,19 @@
  *                III.D), computed by the preconditioned Newton-Schulz
  *                iteration of Algorithm NS_Polar (eqs. (a_def)-(RogueMatrix),
  *                (NewtonSchulz));
+ *   la_inverse -- X with X A = I or A X = I for a full-rank (N, M) A, by the
+ *                Newton-Schulz inversion of Algorithm NS_Inverse (III.D);
  *   la_serve_* -- a continuous-batching server of la_polar requests.
  *
  * Conventions (the paper is silent on all of them):
  *   - real FP32 data, ROW-MAJOR with explicit leading dimensions: element
  *     (i, j) of X with leading dimension ldx is X[i * ldx + j];
- *   - every matrix pointer passed to la_gemm / la_polar is DEVICE memory
- *     owned by the caller; the library never frees or retains it;
+ *   - every matrix pointer passed to la_gemm / la_polar / la_inverse is
+ *     DEVICE memory owned by the caller; the library never frees or retains
+ *     it;
  *   - hip_stream is a hipStream_t (NULL = the legacy default stream); la_gemm
- *     only enqueues work, la_polar blocks on a per-iteration 8-byte readback;
+ *     only enqueues work, la_polar and la_inverse block on a per-iteration
+ *     8-byte readback;
  *   - no exceptions cross the ABI and nothing aborts: every call returns a
  *     la_status; la_last_error() gives a message for the calling thread.
  */
@@ -38,7 +42,7 @@ typedef enum {
     LA_ERR_INVALID_ARG = 1,    /* null pointer, bad enum, aliasing, ...          */
     LA_ERR_SHAPE = 2,          /* negative size, ld < row length, M < N (polar)  */
     LA_ERR_NONFINITE = 3,      /* ||A||_F or a step norm is Inf/NaN, or A == 0   */
-    LA_ERR_NOT_CONVERGED = 4,  /* polar hit max_iter without reaching tolerance  */
+    LA_ERR_NOT_CONVERGED = 4,  /* max_iter reached without meeting the tolerance */
     LA_ERR_OUT_OF_MEMORY = 5,  /* workspace / arena smaller than required        */
     LA_ERR_DEVICE = 6,         /* HIP runtime error or unsupported device        */
     LA_ERR_QUEUE_FULL = 7,     /* serving queue at capacity                      */
@@ -145,6 +149,58 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A,
                    int64_t lda, float *U, int64_t ldu, float *H, int64_t ldh,
                    void *workspace, size_t ws_bytes, const la_polar_opts *opts,
                    la_polar_info *info, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Newton-Schulz matrix inversion (section III.D, Algorithm NS_Inverse).
+ * For an n x m A of full rank it returns the m x n X with X A = I_m
+ * (n >= m) or A X = I_n (n <= m): the inverse when A is square, else the
+ * Moore-Penrose pseudo-inverse.  a = ||A A^T||_F, X0 = A^T / a, then
+ *   X' = X (2I - A X) = (2I - X A) X,   evaluated as X + X (I - A X) when
+ *   n <= m and as X + (I - X A) X when n > m (the smaller product; the two
+ *   are the same polynomial in exact arithmetic),
+ * until the step norm delta = sqrt(a) ||X' - X||_F is at most the
+ * tolerance, which starts at eps and doubles after every step.  (delta is
+ * measured on the normalised problem A / sqrt(a), so the stop does not
+ * depend on the scale of A; literal_delta = 1 compares ||X' - X||_F as the
+ * algorithm prints it.)
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double eps;        /* starting tolerance (unit roundoff)      [2^-24]      */
+    int max_iter;      /* cap on steps                             [100]        */
+    int prec;          /* la_precision of the products; AUTO = BF16X3 steps
+                          followed by one BF16X6 step                 [AUTO] */
+    int polish;        /* 1: one extra step at BF16X6 after the stop (always
+                          on for AUTO)                                    [0] */
+    int literal_delta; /* 1: compare ||X' - X||_F without the sqrt(a) factor [0] */
+    int reserved[4];
+} la_inverse_opts;
+
+typedef struct {
+    int iters;          /* steps taken, polish included                       */
+    int product_side;   /* 1: the step formed A X (n x n, n <= m);
+                           0: it formed X A (m x m, n > m)                    */
+    double gram_norm;   /* a = ||A A^T||_F, accumulated in FP64 on the GPU     */
+    double last_delta;  /* the step norm last compared (FP64)                 */
+    double last_tol;    /* the tolerance it was compared with                 */
+    int stop_reason;    /* 0 tolerance, 2 iteration cap                       */
+    int prec;           /* resolved precision                                 */
+} la_inverse_info;
+
+/* Bytes of device workspace la_inverse needs for an n x m A (0 on bad
+ * arguments).  opts may be NULL. */
+size_t la_inverse_workspace_size(int64_t n, int64_t m, const la_inverse_opts *opts);
+
+/* A (n x m, lda >= m, n, m >= 1) is read only; X (m x n, ldx >= n) receives
+ * the result and must not overlap A or the workspace.  workspace: device
+ * memory of at least la_inverse_workspace_size() bytes, 256-byte aligned.
+ * Runs on hip_stream and returns after the last kernel has completed (one
+ * 8-byte readback per step).  LA_ERR_NONFINITE if a is 0, Inf or NaN or a
+ * step norm is not finite; LA_ERR_NOT_CONVERGED if max_iter steps ran
+ * without meeting the tolerance (X then holds the last iterate).  info may
+ * be NULL. */
+la_status la_inverse(la_context *ctx, int64_t n, int64_t m, const float *A, int64_t lda,
+                     float *X, int64_t ldx, void *workspace, size_t ws_bytes,
+                     const la_inverse_opts *opts, la_inverse_info *info, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of polar requests.

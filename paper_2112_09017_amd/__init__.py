@@ -1,4 +1,5 @@
-"""MI355X (gfx950) FP32-accurate GEMM and Newton-Schulz polar factorisation.
+"""MI355X (gfx950) FP32-accurate GEMM, Newton-Schulz polar factorisation and
+Newton-Schulz inversion.
 
 Python face of the C ABI in ``include/la.h`` (arXiv 2112.09017, sections III.A
 and III.D).  Tensors are torch float32 CUDA (HIP) tensors; a 2-D tensor whose
@@ -12,11 +13,12 @@ import ctypes
 
 import torch
 
-from ._binding import (LAError, PolarInfo, PolarOpts, Precision, ServeConfig, ServeStats,
-                       Status, check, context, lib, make_opts, LIB_PATH, SIGNATURES)
+from ._binding import (InverseInfo, LAError, PolarInfo, PolarOpts, Precision, ServeConfig,
+                       ServeStats, Status, check, context, lib, make_inverse_opts, make_opts,
+                       LIB_PATH, SIGNATURES)
 
-__all__ = ["gemm", "polar", "polar_workspace_size", "Precision", "LAError", "Status",
-           "lib", "LIB_PATH", "Server"]
+__all__ = ["gemm", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
+           "Precision", "LAError", "Status", "lib", "LIB_PATH", "Server"]
 
 
 def _stream_ptr(stream) -> ctypes.c_void_p:
@@ -99,6 +101,47 @@ def polar(A: torch.Tensor, *, want_h: bool = True, U: torch.Tensor | None = None
         return U, H, info.as_dict()
     check(st)
     return U, (H if want_h else None), info.as_dict()
+
+
+def inverse_workspace_size(n: int, m: int, **opts) -> int:
+    o = make_inverse_opts(**opts)
+    return int(lib().la_inverse_workspace_size(n, m, ctypes.byref(o)))
+
+
+def inverse(A: torch.Tensor, *, X: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None, stream=None,
+            raise_not_converged: bool = True, **opts):
+    """X with X A = I (A tall or square) or A X = I (A wide) through
+    ``la_inverse`` (Algorithm NS_Inverse).  Returns (X, info dict).  ``opts``
+    are the fields of ``la_inverse_opts`` (eps, max_iter, prec, polish,
+    literal_delta)."""
+    pa, n, m, lda, ta = _as_matrix(A, "A")
+    if ta:
+        A = A.contiguous()
+        pa, n, m, lda, ta = _as_matrix(A, "A")
+    dev = A.device
+    if X is None:
+        X = torch.empty((m, n), dtype=torch.float32, device=dev)
+    o = make_inverse_opts(**opts)
+    need = int(lib().la_inverse_workspace_size(n, m, ctypes.byref(o)))
+    if need == 0:
+        raise LAError(Status.SHAPE, f"bad inverse shape {n} x {m}")
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wp = workspace.data_ptr()
+    wp_al = (wp + 255) & ~255
+    avail = max(workspace.numel() - (wp_al - wp), 0)   # a short one is reported by the library
+    px, mx, nx, ldx, tx = _as_matrix(X, "X")
+    if (mx, nx) != (m, n) or tx:
+        raise ValueError("X must be a row-major m x n tensor")
+    info = InverseInfo()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    st = lib().la_inverse(ctx, n, m, pa, lda, px, ldx, wp_al, avail, ctypes.byref(o),
+                          ctypes.byref(info), _stream_ptr(stream))
+    if st == Status.NOT_CONVERGED and not raise_not_converged:
+        return X, info.as_dict()
+    check(st)
+    return X, info.as_dict()
 
 
 from .serve import Server  # noqa: E402

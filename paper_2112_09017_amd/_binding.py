@@ -77,6 +77,32 @@ class PolarInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class InverseOpts(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("polish", ctypes.c_int),
+        ("literal_delta", ctypes.c_int),
+        ("reserved", ctypes.c_int * 4),
+    ]
+
+
+class InverseInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("product_side", ctypes.c_int),
+        ("gram_norm", ctypes.c_double),
+        ("last_delta", ctypes.c_double),
+        ("last_tol", ctypes.c_double),
+        ("stop_reason", ctypes.c_int),
+        ("prec", ctypes.c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServeConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int), ("max_queue", ctypes.c_int),
                 ("reserved", ctypes.c_int * 6)]
@@ -113,6 +139,9 @@ SIGNATURES = {
     "la_polar": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
                                 ctypes.c_size_t, ctypes.POINTER(PolarOpts),
                                 ctypes.POINTER(PolarInfo), _VP]),
+    "la_inverse_workspace_size": (ctypes.c_size_t, [_I64, _I64, ctypes.POINTER(InverseOpts)]),
+    "la_inverse": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, ctypes.c_size_t,
+                                  ctypes.POINTER(InverseOpts), ctypes.POINTER(InverseInfo), _VP]),
     "la_serve_create": (ctypes.c_int, [_VP, ctypes.POINTER(ServeConfig), _VP, ctypes.c_size_t,
                                        ctypes.POINTER(_VP)]),
     "la_serve_submit": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, ctypes.POINTER(PolarOpts),
@@ -176,4 +205,15 @@ def make_opts(s_minus=0.0, s0=0.0, eps=0.0, max_iter=0, prec_precond=Precision.A
     o.prec_h = int(prec_h)
     o.polish = 1 if polish else 0
     o.no_stagnation = 0 if stagnation else 1
+    return o
+
+
+def make_inverse_opts(eps=0.0, max_iter=0, prec=Precision.AUTO, polish=False,
+                      literal_delta=False) -> InverseOpts:
+    o = InverseOpts()
+    o.eps = eps
+    o.max_iter = max_iter
+    o.prec = int(prec)
+    o.polish = 1 if polish else 0
+    o.literal_delta = 1 if literal_delta else 0
     return o

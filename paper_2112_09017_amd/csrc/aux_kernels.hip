@@ -4,6 +4,8 @@
 // precision dispatch of the GEMM launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "la_internal.h"
 
 namespace la {
@@ -163,6 +165,32 @@ __global__ void scale_kernel(const float *__restrict__ X, int64_t ldx, float *__
             Y[r * ldy + c] = (float)((double)X[r * ldx + c] / nrm);
 }
 
+// X = A^T / a for an n x m A (X is m x n): 32 x 32 tiles staged through LDS
+// (padded rows) so that both the read of A and the write of X are coalesced.
+// The division is done in FP64 and rounded once, as in scale_kernel.
+__global__ void transpose_scale_kernel(const float *__restrict__ A, int64_t lda,
+                                       float *__restrict__ X, int64_t ldx, int64_t n,
+                                       int64_t m, double a)
+{
+    __shared__ float t[32][33];
+    const int64_t tiles_m = (m + 31) / 32;
+    for (int64_t bm = blockIdx.y; bm < tiles_m; bm += gridDim.y) {
+        const int64_t i0 = (int64_t)blockIdx.x * 32;   // rows of A = columns of X
+        const int64_t j0 = bm * 32;                     // columns of A = rows of X
+        for (int r = threadIdx.y; r < 32; r += 8) {
+            const int64_t i = i0 + r, j = j0 + threadIdx.x;
+            t[r][threadIdx.x] = (i < n && j < m) ? A[i * lda + j] : 0.0f;
+        }
+        __syncthreads();
+        for (int r = threadIdx.y; r < 32; r += 8) {
+            const int64_t row = j0 + r, col = i0 + threadIdx.x;
+            if (row < m && col < n)
+                X[row * ldx + col] = (float)((double)t[threadIdx.x][r] / a);
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void copy_kernel(const float *__restrict__ X, int64_t ldx, float *__restrict__ Y,
                             int64_t ldy, int64_t m, int64_t n)
 {
@@ -250,6 +278,20 @@ hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy, int6
         return hipSuccess;
     hipLaunchKernelGGL(scale_kernel, grid2d(m, n), dim3(kThreads), 0, s, X, ldx, Y, ldy, m, n,
                        nrm);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t ldx, int64_t n,
+                                  int64_t m, double a, hipStream_t s)
+{
+    if (m == 0 || n == 0)
+        return hipSuccess;
+    const int64_t tn = (n + 31) / 32, tm = (m + 31) / 32;
+    if (tn > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const unsigned gy = (unsigned)std::min<int64_t>(tm, 65535);
+    hipLaunchKernelGGL(transpose_scale_kernel, dim3((unsigned)tn, gy), dim3(32, 8), 0, s, A, lda,
+                       X, ldx, n, m, a);
     return hipGetLastError();
 }
 

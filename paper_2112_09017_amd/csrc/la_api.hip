@@ -1,4 +1,5 @@
-// C ABI: context, error reporting, la_gemm and the la_polar driver.
+// C ABI: context, error reporting, la_gemm, the la_polar driver and the
+// la_inverse driver (Algorithm NS_Inverse, at the end of this file).
 //
 // la_polar follows Algorithm NS_Polar (section III.D of arXiv 2112.09017):
 //   U <- A / ||A||_F                                   (FP64 norm on the GPU)
@@ -277,6 +278,173 @@ static hipError_t update_step(int prec, const float *X, int64_t ldx, const float
     if (ntiles)
         *ntiles = d.tiles_m * d.tiles_n;
     return launch_gemm(prec, d, s);
+}
+
+// ------------------------------------------------------------------ inverse
+
+// Algorithm NS_Inverse (section III.D) for an n x m A: X0 = A^T / ||A A^T||_F,
+// X' = X (2I - A X) = (2I - X A) X.  The step forms the smaller product:
+// A X (n x n) when n <= m, X A (m x m) when n > m.
+struct InvPlan {
+    int64_t n, m;
+    int64_t r;       // side of the formed product
+    int wide;        // 1: n <= m (forms A X); 0: n > m (forms X A)
+    double eps;
+    int max_iter, polish, literal;
+    int prec;
+};
+
+static la_status inverse_plan(int64_t n, int64_t m, const la_inverse_opts *opts, InvPlan *out)
+{
+    if (n < 1 || m < 1) {
+        set_error("la_inverse: sizes must be positive (n %lld, m %lld)", (long long)n,
+                  (long long)m);
+        return LA_ERR_SHAPE;
+    }
+    la_inverse_opts o;
+    memset(&o, 0, sizeof o);
+    if (opts)
+        o = *opts;
+    if (!valid_prec(o.prec)) {
+        set_error("la_inverse: unknown precision %d", o.prec);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (!(o.eps >= 0.0) || !isfinite(o.eps) || o.max_iter < 0) {
+        set_error("la_inverse: bad eps or max_iter");
+        return LA_ERR_INVALID_ARG;
+    }
+    InvPlan p;
+    p.n = n;
+    p.m = m;
+    p.wide = n <= m;
+    p.r = p.wide ? n : m;
+    p.eps = o.eps > 0.0 ? o.eps : ldexp(1.0, -24);
+    p.max_iter = o.max_iter > 0 ? o.max_iter : 100;
+    // AUTO: 3xBF16 steps, then one 6xBF16 step.  Forming I - A X near the
+    // fixed point cancels to O(1) from terms of size ~cond(A), so the dropped
+    // lo*lo products of 3xBF16 (2^-18 relative) limit its accuracy; the
+    // iteration converges quadratically, so one 6xBF16 step restores FP32-level
+    // accuracy.
+    p.polish = o.polish != 0 || o.prec == LA_PREC_AUTO;
+    p.literal = o.literal_delta != 0;
+    p.prec = resolve(o.prec, PREC_BF16X3);
+    *out = p;
+    return LA_OK;
+}
+
+static size_t inverse_max_tiles(const InvPlan &p)
+{
+    size_t t = 0;
+    for (int pr : {PREC_FP32, PREC_BF16X3, PREC_BF16X6}) {
+        const size_t tm = (size_t)((p.m + tile_m(pr, 1) - 1) / tile_m(pr, 1));
+        const size_t tn = (size_t)((p.n + tile_n(pr, 1) - 1) / tile_n(pr, 1));
+        t = std::max(t, tm * tn);
+    }
+    return t;
+}
+
+struct InvWs {
+    float *X;        // m x n, ld n: the iterate's second buffer
+    float *R;        // r x r: the Gram A A^T (or A^T A), then I - A X (or I - X A)
+    double *tiles;   // per-tile step-norm partials
+    double *sumsq;   // norm partials
+    double *scal;    // [0] ||A A^T||_F^2, [1] ||X' - X||_F^2
+};
+
+static size_t inverse_workspace_bytes(const InvPlan &p)
+{
+    size_t b = 0;
+    b += align256((size_t)p.m * p.n * sizeof(float));
+    b += align256((size_t)p.r * p.r * sizeof(float));
+    b += align256(inverse_max_tiles(p) * sizeof(double));
+    b += align256((size_t)sumsq_num_partials() * sizeof(double));
+    b += align256(8 * sizeof(double));
+    return b;
+}
+
+static InvWs inverse_carve(const InvPlan &p, void *ws)
+{
+    InvWs w;
+    char *b = (char *)ws;
+    w.X = (float *)b;
+    b += align256((size_t)p.m * p.n * sizeof(float));
+    w.R = (float *)b;
+    b += align256((size_t)p.r * p.r * sizeof(float));
+    w.tiles = (double *)b;
+    b += align256(inverse_max_tiles(p) * sizeof(double));
+    w.sumsq = (double *)b;
+    b += align256((size_t)sumsq_num_partials() * sizeof(double));
+    w.scal = (double *)b;
+    return w;
+}
+
+// One step X' = X + X (I - A X)  (wide / square)  or  X + (I - X A) X  (tall),
+// with FP64 per-tile partials of (X' - X)^2 in w.tiles.
+static hipError_t inverse_step(const InvPlan &p, int prec, const float *A, int64_t lda,
+                               const float *X, int64_t ldx, float *Xn, int64_t ldxn,
+                               const InvWs &w, int *ntiles, hipStream_t s)
+{
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.C = w.R;
+    d.ldc = p.r;
+    d.M = p.r;
+    d.N = p.r;
+    d.alpha = -1.0f;
+    d.gamma = 1.0f;
+    if (p.wide) {               // R = I - A X: A (n x m) . X (m x n)
+        d.A = A;
+        d.lda = lda;
+        d.a_kcontig = 1;
+        d.B = X;
+        d.ldb = ldx;
+        d.b_kcontig = 0;
+        d.K = p.m;
+    } else {                    // R = I - X A: X (m x n) . A (n x m)
+        d.A = X;
+        d.lda = ldx;
+        d.a_kcontig = 1;
+        d.B = A;
+        d.ldb = lda;
+        d.b_kcontig = 0;
+        d.K = p.n;
+    }
+    gemm_finalize(d, prec);
+    hipError_t e = launch_gemm(prec, d, s);
+    if (e != hipSuccess)
+        return e;
+
+    GemmDesc u;
+    memset(&u, 0, sizeof u);
+    u.C = Xn;
+    u.ldc = ldxn;
+    u.M = p.m;
+    u.N = p.n;
+    u.alpha = 1.0f;
+    u.beta = 1.0f;
+    u.E = X;
+    u.lde = ldx;
+    u.partials = w.tiles;
+    if (p.wide) {               // X' = X + X R: X (m x n) . R (n x n)
+        u.A = X;
+        u.lda = ldx;
+        u.a_kcontig = 1;
+        u.B = w.R;
+        u.ldb = p.r;
+        u.b_kcontig = 0;
+        u.K = p.n;
+    } else {                    // X' = X + R X: R (m x m) . X (m x n)
+        u.A = w.R;
+        u.lda = p.r;
+        u.a_kcontig = 1;
+        u.B = X;
+        u.ldb = ldx;
+        u.b_kcontig = 0;
+        u.K = p.m;
+    }
+    gemm_finalize(u, prec);
+    *ntiles = u.tiles_m * u.tiles_n;
+    return launch_gemm(prec, u, s);
 }
 
 }  // namespace la
@@ -569,6 +737,155 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
     if (!stopped) {
         set_error("la_polar: no convergence after %d Newton-Schulz steps (delta %g)",
                   inf.iters_ns, inf.last_delta);
+        return LA_ERR_NOT_CONVERGED;
+    }
+    return LA_OK;
+}
+
+size_t la_inverse_workspace_size(int64_t n, int64_t m, const la_inverse_opts *opts)
+{
+    InvPlan p;
+    if (inverse_plan(n, m, opts, &p) != LA_OK)
+        return 0;
+    return inverse_workspace_bytes(p);
+}
+
+la_status la_inverse(la_context *ctx, int64_t n, int64_t m, const float *A, int64_t lda,
+                     float *X, int64_t ldx, void *workspace, size_t ws_bytes,
+                     const la_inverse_opts *opts, la_inverse_info *info, void *hip_stream)
+{
+    g_err[0] = 0;
+    InvPlan p;
+    la_status st = inverse_plan(n, m, opts, &p);
+    if (st != LA_OK)
+        return st;
+    if (lda < m || ldx < n) {
+        set_error("la_inverse: leading dimension too small (lda %lld < m or ldx %lld < n)",
+                  (long long)lda, (long long)ldx);
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx || !A || !X || !workspace) {
+        set_error("la_inverse: NULL argument");
+        return LA_ERR_INVALID_ARG;
+    }
+    if (((uintptr_t)workspace & 255u) != 0) {
+        set_error("la_inverse: workspace must be 256-byte aligned");
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t need = inverse_workspace_bytes(p);
+    if (ws_bytes < need) {
+        set_error("la_inverse: workspace %zu bytes, need %zu", ws_bytes, need);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    const size_t ab = extent_bytes(n, m, lda), xb = extent_bytes(m, n, ldx);
+    if (overlaps(X, xb, A, ab) || overlaps(X, xb, workspace, need)) {
+        set_error("la_inverse: X overlaps A or the workspace");
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_inverse: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    InvWs w = inverse_carve(p, workspace);
+
+    la_inverse_info inf;
+    memset(&inf, 0, sizeof inf);
+    inf.product_side = p.wide;
+    inf.prec = p.prec;
+    inf.last_delta = INFINITY;
+    inf.stop_reason = 2;
+
+    // a = ||A A^T||_F = ||A^T A||_F, from the smaller symmetric Gram (FP64 norm)
+    {
+        GemmDesc g;
+        memset(&g, 0, sizeof g);
+        g.A = A;
+        g.B = A;
+        g.lda = lda;
+        g.ldb = lda;
+        g.C = w.R;
+        g.ldc = p.r;
+        g.M = p.r;
+        g.N = p.r;
+        g.alpha = 1.0f;
+        g.gram = 1;
+        if (p.wide) {           // A A^T: op(A)(i, k) = A[i][k], op(B)(k, j) = A[j][k]
+            g.a_kcontig = 1;
+            g.b_kcontig = 1;
+            g.K = p.m;
+        } else {                // A^T A: op(A)(i, k) = A[k][i], op(B)(k, j) = A[k][j]
+            g.a_kcontig = 0;
+            g.b_kcontig = 0;
+            g.K = p.n;
+        }
+        gemm_finalize(g, p.prec);
+        LA_HIP(launch_gemm(p.prec, g, s), "la_inverse: gram");
+    }
+    double h2[2];
+    LA_HIP(launch_sumsq(w.R, p.r, p.r, p.r, w.sumsq, s), "la_inverse: norm");
+    LA_HIP(launch_reduce_fixed(w.sumsq, sumsq_num_partials(), w.scal, s), "la_inverse: norm");
+    LA_HIP(hipMemcpyAsync(h2, w.scal, sizeof(double), hipMemcpyDeviceToHost, s),
+           "la_inverse: readback");
+    LA_HIP(hipStreamSynchronize(s), "la_inverse: sync");
+    const double a = sqrt(h2[0]);
+    inf.gram_norm = a;
+    if (!(a > 0.0) || !isfinite(a)) {
+        if (info)
+            *info = inf;
+        set_error("la_inverse: ||A A^T||_F = %g (zero or not finite)", a);
+        return LA_ERR_NONFINITE;
+    }
+
+    // X0 = A^T / a; ping-pong between X (ld ldx) and the workspace copy (ld n)
+    float *buf[2] = {X, w.X};
+    int64_t ld[2] = {ldx, n};
+    int cur = 0;
+    LA_HIP(launch_transpose_scale(A, lda, buf[cur], ld[cur], n, m, a, s), "la_inverse: X0");
+
+    const double scale = p.literal ? 1.0 : sqrt(a);
+    double eps = p.eps;
+    const int total = p.max_iter + (p.polish ? 1 : 0);
+    bool stopped = false;
+    for (int it = 0; it < total; ++it) {
+        const bool polishing = stopped;
+        const int prec = polishing ? PREC_BF16X6 : p.prec;
+        int ntiles = 0;
+        LA_HIP(inverse_step(p, prec, A, lda, buf[cur], ld[cur], buf[cur ^ 1], ld[cur ^ 1], w,
+                            &ntiles, s),
+               "la_inverse: step");
+        LA_HIP(launch_reduce_fixed(w.tiles, ntiles, w.scal + 1, s), "la_inverse: delta");
+        LA_HIP(hipMemcpyAsync(h2 + 1, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s),
+               "la_inverse: readback");
+        LA_HIP(hipStreamSynchronize(s), "la_inverse: sync");
+        cur ^= 1;
+        inf.iters++;
+        const double delta = scale * sqrt(h2[1]);
+        if (!isfinite(delta)) {
+            if (info)
+                *info = inf;
+            set_error("la_inverse: step norm is not finite");
+            return LA_ERR_NONFINITE;
+        }
+        if (polishing)
+            break;
+        eps *= 2.0;                 // the tolerance grows after every step
+        inf.last_delta = delta;
+        inf.last_tol = eps;
+        if (!(delta > eps)) {
+            inf.stop_reason = 0;
+            stopped = true;
+        }
+        if (stopped && !p.polish)
+            break;
+        if (!stopped && it + 1 >= p.max_iter)
+            break;
+    }
+    if (cur != 0)
+        LA_HIP(launch_copy(buf[cur], ld[cur], X, ldx, m, n, s), "la_inverse: copy");
+    LA_HIP(hipStreamSynchronize(s), "la_inverse: final sync");
+    if (info)
+        *info = inf;
+    if (!stopped) {
+        set_error("la_inverse: tolerance not met after %d steps (delta %g, tol %g)", inf.iters,
+                  inf.last_delta, inf.last_tol);
         return LA_ERR_NOT_CONVERGED;
     }
     return LA_OK;

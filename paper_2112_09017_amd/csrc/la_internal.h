@@ -79,6 +79,9 @@ hipError_t launch_reduce_fixed(const double *parts, int64_t count, double *out,
 // power of two leaves Y bitwise unchanged).
 hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy,
                         int64_t m, int64_t n, double nrm, hipStream_t s);
+// X = A^T / a (FP64 division, rounded once); A is n x m, X is m x n.
+hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t ldx,
+                                  int64_t n, int64_t m, double a, hipStream_t s);
 // Y = X (strided copy).
 hipError_t launch_copy(const float *X, int64_t ldx, float *Y, int64_t ldy,
                        int64_t m, int64_t n, hipStream_t s);

@@ -25,7 +25,7 @@ def L():
 def test_header_declares_expected_api():
     names = declared_functions()
     for n in ("la_create", "la_destroy", "la_gemm", "la_polar", "la_polar_workspace_size",
-              "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
+              "la_inverse", "la_inverse_workspace_size", "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
               "la_status_string", "la_last_error"):
         assert n in names
 
@@ -71,6 +71,26 @@ def test_polar_argument_validation_without_device(L):
     assert L.la_polar(None, 3, 5, None, 5, None, 5, None, 5, None, 0, None, None, None) == 2
     assert L.la_polar(None, 8, 8, None, 4, None, 8, None, 8, None, 0, None, None, None) == 2
     assert L.la_polar(None, 8, 8, None, 8, None, 8, None, 8, None, 0, None, None, None) == 1
+
+
+def test_inverse_argument_validation_without_device(L):
+    from paper_2112_09017_amd import _binding
+    assert L.la_inverse_workspace_size(0, 4, None) == 0
+    assert L.la_inverse_workspace_size(4, -1, None) == 0
+    tall = L.la_inverse_workspace_size(300, 200, None)      # X is 200 x 300, product 200 x 200
+    assert tall >= 4 * (300 * 200 + 200 * 200)
+    wide = L.la_inverse_workspace_size(200, 300, None)      # product 200 x 200 as well
+    assert wide >= 4 * (300 * 200 + 200 * 200)
+    o = _binding.make_inverse_opts(prec=9)
+    assert L.la_inverse_workspace_size(8, 8, ctypes.byref(o)) == 0
+    o = _binding.make_inverse_opts(eps=-1.0)
+    assert L.la_inverse_workspace_size(8, 8, ctypes.byref(o)) == 0
+    # sizes, leading dimensions, then NULL arguments
+    assert L.la_inverse(None, 0, 4, None, 4, None, 0, None, 0, None, None, None) == 2
+    assert L.la_inverse(None, 8, 6, None, 5, None, 8, None, 0, None, None, None) == 2
+    assert L.la_inverse(None, 8, 6, None, 6, None, 7, None, 0, None, None, None) == 2
+    assert L.la_inverse(None, 8, 6, None, 6, None, 8, None, 0, None, None, None) == 1
+    assert L.la_last_error() == b"la_inverse: NULL argument"
 
 
 def test_create_reports_missing_device(L):

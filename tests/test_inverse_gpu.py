@@ -1,0 +1,213 @@
+"""la_inverse on the GPU against the FP64 oracle (Algorithm NS_Inverse).
+
+Tolerance, derived from the GEMM target: every product is FP32-accurate to a
+normwise relative error g <= 1e-6.  At the fixed point the computed residual
+I - A X carries an error of about g ||A|| ||X|| ~ g cond(A), and
+X - A^-1 = A^-1 (I - A X), so ||X - A^-1||_F / ||A^-1||_F <= 2 g cond(A) with
+g = 1e-6 (a factor 2 for the last correction).  The one-sided residual is
+I - A X = A (A^-1 - X), at most cond(A) times that: 2 g cond(A)^2.  The
+oracle runs the same algorithm in FP64 with the same starting tolerance (the
+FP32 unit roundoff 2^-24), so the step counts are compared too.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import la_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+G = 1e-6
+U24 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def la():
+    import paper_2112_09017_amd as la
+    la.lib()
+    return la
+
+
+def run(la, A32, **opts):
+    X, info = la.inverse(torch.from_numpy(np.ascontiguousarray(A32)).to("cuda"), **opts)
+    torch.cuda.synchronize()
+    return X.cpu().numpy().astype(np.float64), info
+
+
+def cond2(A):
+    s = np.linalg.svd(A, compute_uv=False)
+    return float(s[0] / s[-1])
+
+
+def one_sided_residual(A, X):
+    n, m = A.shape
+    if n >= m:
+        return np.linalg.norm(X @ A - np.eye(m)) / math.sqrt(m)
+    return np.linalg.norm(A @ X - np.eye(n)) / math.sqrt(n)
+
+
+POLICIES = {
+    "auto": {},
+    "fp32": dict(prec=1),
+    "x6": dict(prec=3),
+    "auto_polish": dict(polish=True),
+}
+
+
+@pytest.mark.parametrize("policy", sorted(POLICIES))
+@pytest.mark.parametrize("lo", [1e-1, 1e-3])
+def test_square_vs_oracle(la, policy, lo):
+    """256 x 256 (and a ragged 300 x 300), Q diag(s) V^T, s log-uniform in [lo, 1]."""
+    for n, seeds in ((256, (130, 131, 132)), (300, (133, 134, 135))):
+        case = la_inputs.polar_case(n, n, lo, seeds=seeds)
+        A = case.A32.astype(np.float64)
+        X, info = run(la, case.A32, **POLICIES[policy])
+        Xo, io = oracle.inverse(A, u=U24)
+        kappa = cond2(A)
+        err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+        res = one_sided_residual(A, X)
+        print(f"\n{policy} n={n} cond={kappa:.3g}: rel err {err:.3g} resid {res:.3g} "
+              f"iters {info['iters']} (oracle {io.iters}) bound {2 * G * kappa:.3g}")
+        assert err <= 2 * G * kappa
+        assert res <= 2 * G * kappa ** 2
+        extra = 1 if (POLICIES[policy].get("polish") or not POLICIES[policy]) else 0
+        assert abs(info["iters"] - extra - io.iters) <= 2
+        assert info["product_side"] == 1
+        assert info["stop_reason"] == 0
+        assert abs(info["gram_norm"] - io.gram_norm) <= 1e-5 * io.gram_norm
+        # the oracle stops at the FP32 starting tolerance, i.e. within ~1e-9 of A^-1
+        assert np.linalg.norm(Xo - np.linalg.inv(A)) <= 1e-8 * np.linalg.norm(Xo)
+
+
+@pytest.mark.parametrize("shape", [(520, 200), (200, 520), (300, 257), (257, 300), (1, 1),
+                                   (7, 1), (1, 7), (64, 33)])
+def test_rectangular_and_ragged(la, shape):
+    """Tall: X A = I (left inverse); wide: A X = I (right inverse); both equal
+    the pseudo-inverse for a full-rank A."""
+    n, m = shape
+    A32 = la_inputs.gaussian(shape, 140 + n + 3 * m)
+    A = A32.astype(np.float64)
+    X, info = run(la, A32)
+    assert X.shape == (m, n)
+    Xo, io = oracle.inverse(A, u=U24)
+    kappa = cond2(A)
+    P = np.linalg.pinv(A)
+    err = np.linalg.norm(X - P) / np.linalg.norm(P)
+    res = one_sided_residual(A, X)
+    print(f"\n{shape}: cond {kappa:.3g} rel err {err:.3g} resid {res:.3g} iters {info['iters']} "
+          f"(oracle {io.iters})")
+    assert err <= 2 * G * max(kappa, 1.0)
+    assert res <= 2 * G * max(kappa, 1.0) ** 2
+    assert info["product_side"] == (1 if n <= m else 0)
+    # AUTO adds one 6xBF16 step.  The 3xBF16 step norm has a floor of about
+    # 2^-17 on the normalised problem, below which it cannot fall until the
+    # doubling tolerance 2^(k-24) passes it (k ~ 7); the FP64 oracle has no such
+    # floor and can stop after one step when X0 is already the pseudo-inverse.
+    k = info["iters"] - 1
+    assert io.iters - 2 <= k <= max(io.iters, 8) + 2
+
+
+def test_special_cases(la):
+    n = 96
+    I = np.eye(n, dtype=np.float32)
+    X, info = run(la, I)
+    assert np.max(np.abs(X - np.eye(n))) < 1e-6
+    Q = la_inputs.haar(n, 150).astype(np.float32)
+    X, _ = run(la, Q)
+    assert np.max(np.abs(X - Q.astype(np.float64).T)) < 1e-5
+    d = np.exp(la_inputs.rng(151).uniform(np.log(1e-2), 0.0, size=n)).astype(np.float32)
+    X, _ = run(la, np.diag(d))
+    assert np.max(np.abs(np.diag(X) * d - 1.0)) < 2 * G * 100
+    assert np.max(np.abs(X - np.diag(np.diag(X)))) < 1e-6 * np.max(np.abs(X))
+
+
+def test_scale_invariance_bitwise(la):
+    """A -> 2^k A scales a by 2^(2k) and X0 by 2^-k exactly; every product and
+    the normalised step norm then scale exactly, so X -> 2^-k X bitwise with
+    the same step count."""
+    case = la_inputs.polar_case(192, 192, 1e-2, seeds=(152, 153, 154))
+    X, info = run(la, case.A32)
+    for k in (-7, 5):
+        Xk, ik = run(la, case.A32 * np.float32(2.0 ** k))
+        assert ik["iters"] == info["iters"]
+        assert np.array_equal(Xk, X * 2.0 ** -k)
+
+
+def test_literal_delta_reading(la):
+    """With the printed (unnormalised) step norm the stop depends on the scale
+    of A: for A scaled by 2^10 it stops earlier, as the oracle's literal
+    reading does."""
+    case = la_inputs.polar_case(128, 128, 1e-2, seeds=(155, 156, 157))
+    A32 = case.A32 * np.float32(1024.0)
+    X, info = run(la, A32, literal_delta=True)
+    Xn, infn = run(la, A32)
+    _, io = oracle.inverse(A32.astype(np.float64), u=U24, normalize=False)
+    assert abs(info["iters"] - 1 - io.iters) <= 2
+    assert info["iters"] < infn["iters"]
+
+
+def test_determinism(la):
+    case = la_inputs.polar_case(256, 256, 1e-2, seeds=(158, 159, 160))
+    X1, i1 = run(la, case.A32)
+    X2, i2 = run(la, case.A32)
+    assert np.array_equal(X1, X2)
+    assert i1 == i2
+
+
+def test_error_paths(la):
+    from paper_2112_09017_amd import LAError, Status
+    with pytest.raises(LAError) as e:
+        run(la, np.zeros((16, 16), np.float32))
+    assert e.value.status == Status.NONFINITE
+    bad = la_inputs.gaussian((16, 16), 161)
+    bad[3, 4] = np.nan
+    with pytest.raises(LAError) as e:
+        run(la, bad)
+    assert e.value.status == Status.NONFINITE
+    case = la_inputs.polar_case(64, 64, 1e-3, seeds=(162, 163, 164))
+    with pytest.raises(LAError) as e:
+        run(la, case.A32, max_iter=2)
+    assert e.value.status == Status.NOT_CONVERGED
+    X, info = run(la, case.A32, max_iter=2, raise_not_converged=False)
+    assert info["iters"] == 2 and info["stop_reason"] == 2 and np.all(np.isfinite(X))
+    X, info = run(la, case.A32, max_iter=2, prec=2, raise_not_converged=False)
+    assert info["iters"] == 2
+    A = torch.from_numpy(case.A32).to("cuda")
+    with pytest.raises(LAError) as e:
+        la.inverse(A, X=A)                         # X aliases A
+    assert e.value.status == Status.INVALID_ARG
+    with pytest.raises(LAError) as e:
+        la.inverse(A, workspace=torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == Status.OUT_OF_MEMORY
+
+
+def _probe_residual(A, X, k=32, seed=170):
+    """||I - A X||_F / sqrt(n) estimated with k Gaussian probes in FP64 on the
+    host: E ||(A X - I) g||^2 = ||A X - I||_F^2 for g ~ N(0, I)."""
+    g = la_inputs.rng(seed).standard_normal(size=(A.shape[1], k))
+    y = A @ (X @ g) - g
+    return math.sqrt(float(np.sum(y * y)) / k) / math.sqrt(A.shape[0])
+
+
+def test_full_size_8192(la):
+    """8192 x 8192, cond 100 (s log-uniform in [1e-2, 1]): the one-sided
+    residual by probes, within the bound and no worse than the all-FP32-MFMA
+    policy's (1.25x, the probe estimate's spread at k = 32)."""
+    n = 8192
+    A32, Q, s, V = la_inputs.polar_case_torch(n, n, 1e-2, (611, 612, 613))
+    del Q, V
+    torch.cuda.empty_cache()
+    Ad = torch.from_numpy(A32).to("cuda")
+    A = A32.astype(np.float64)
+    res = {}
+    for name, opts in (("auto", {}), ("fp32", dict(prec=1))):
+        X, info = la.inverse(Ad, **opts)
+        res[name] = _probe_residual(A, X.cpu().numpy().astype(np.float64))
+        print(f"\n8192 {name}: iters {info['iters']} residual ~{res[name]:.3g}")
+        assert info["stop_reason"] == 0
+        del X
+    assert res["auto"] <= 2 * G * 100.0 ** 2
+    assert res["auto"] <= 1.25 * res["fp32"]
