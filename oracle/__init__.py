@@ -10,6 +10,9 @@ GPU library computes, written from the paper (arXiv 2112.09017):
                    (eqs. PolarDecomp, SVDdef);
 * ``inverse``   -- Algorithm NS_Inverse (Newton-Schulz inversion), with its
                    scalar step ``inv_map``;
+* ``matfunc_odd``  -- odd polynomial of the singular values (eq. OddPoly);
+* ``matfunc_cheb`` -- Chebyshev polynomial of the eigenvalues
+                   (eq. EigenvaluePolynomial);
 * scalar maps   -- eqs. (NS_scalar), (a_def), (RogueScalar) and the
                    preconditioning step count of Algorithm NS_Polar.
 
@@ -100,6 +103,11 @@ def _bind(path: str):
     lib.orc_inverse.argtypes = [i64, i64, dp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 dp, i64, ctypes.c_void_p]
     lib.orc_inverse.restype = ctypes.c_int
+    lib.orc_matfunc_odd.argtypes = [i64, i64, dp, i64, dp, ctypes.c_int, dp, i64]
+    lib.orc_matfunc_odd.restype = ctypes.c_int
+    lib.orc_matfunc_cheb.argtypes = [i64, dp, i64, ctypes.c_double, ctypes.c_double, dp,
+                                     ctypes.c_int, dp, i64]
+    lib.orc_matfunc_cheb.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     return lib
@@ -225,6 +233,29 @@ class Oracle:
         return X, InverseInfo(info.iters, _REASONS.get(info.stop_reason, "?"), info.gram_norm,
                               info.last_delta, info.last_tol)
 
+    def matfunc_odd(self, A, coef):
+        """F = sum_j coef[j] A (A^T A)^j in FP64 (eq. OddPoly)."""
+        A = _f64(A)
+        c = _f64(coef).ravel()
+        m, n = A.shape
+        F = np.zeros((m, n), np.float64)
+        if self._lib.orc_matfunc_odd(m, n, _ptr(A), n, _ptr(c), len(c), _ptr(F), n) != 0:
+            raise ValueError("orc_matfunc_odd: bad arguments or allocation failure")
+        return F
+
+    def matfunc_cheb(self, A, lo, hi, coef):
+        """F = sum_k coef[k] T_k((2A - (lo+hi) I) / (hi - lo)) in FP64
+        (eq. EigenvaluePolynomial); coef[0] carries full weight."""
+        A = _f64(A)
+        c = _f64(coef).ravel()
+        n = A.shape[0]
+        if A.shape != (n, n):
+            raise ValueError("A must be square")
+        F = np.zeros((n, n), np.float64)
+        if self._lib.orc_matfunc_cheb(n, _ptr(A), n, lo, hi, _ptr(c), len(c), _ptr(F), n) != 0:
+            raise ValueError("orc_matfunc_cheb: bad arguments or allocation failure")
+        return F
+
     def polar_2x2(self, A):
         """Closed-form polar factors (U, H) of a full-rank 2 x 2 matrix."""
         A = _f64(A).reshape(2, 2)
@@ -273,6 +304,14 @@ def inv_map(*a, **k):
 
 def inverse(*a, **k):
     return _load().inverse(*a, **k)
+
+
+def matfunc_odd(*a, **k):
+    return _load().matfunc_odd(*a, **k)
+
+
+def matfunc_cheb(*a, **k):
+    return _load().matfunc_cheb(*a, **k)
 
 
 def num_threads():

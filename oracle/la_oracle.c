@@ -394,3 +394,95 @@ int orc_inverse(int64_t n, int64_t m, const double *A, int64_t lda, double u,
     if (info) *info = loc;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Polynomial matrix functions (section III.D, eqs. OddPoly and             */
+/* EigenvaluePolynomial).                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Odd polynomial acting on the singular values (eqs. MatFunc, odd_power,
+ * OddPoly): for an m x n A,
+ *   F = sum_{j=0}^{ncoef-1} c[j] A (A^T A)^j
+ * i.e. f(x) = c[0] x + c[1] x^3 + c[2] x^5 + ...  Evaluated by its
+ * definition: the terms A (A^T A)^j are formed one after another
+ * (term <- term G, G = A^T A) and accumulated.  F is m x n (ldf >= n).
+ * Returns 0 or -1.
+ */
+int orc_matfunc_odd(int64_t m, int64_t n, const double *A, int64_t lda,
+                    const double *c, int ncoef, double *F, int64_t ldf)
+{
+    if (m < 1 || n < 1 || lda < n || ldf < n || ncoef < 1 || !c)
+        return -1;
+    double *G = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *T = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *Tn = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    if (!G || !T || !Tn) {
+        free(G); free(T); free(Tn);
+        return -1;
+    }
+    orc_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, G, n);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            T[i * n + j] = A[i * lda + j];
+            F[i * ldf + j] = c[0] * A[i * lda + j];
+        }
+    for (int p = 1; p < ncoef; ++p) {
+        orc_gemm(0, 0, m, n, n, 1.0, T, n, G, n, 0.0, Tn, n);
+        double *t = T; T = Tn; Tn = t;
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                F[i * ldf + j] += c[p] * T[i * n + j];
+    }
+    free(G); free(T); free(Tn);
+    return 0;
+}
+
+/*
+ * Chebyshev polynomial acting on the eigenvalues (eqs. MatFuncEig,
+ * any_power, EigenvaluePolynomial): for an n x n A whose eigenvalues lie in
+ * [lo, hi],
+ *   F = sum_{k=0}^{ncoef-1} c[k] T_k(B),  B = (2 A - (lo + hi) I) / (hi - lo)
+ * (c[0] carries full weight).  Evaluated by its definition: T_0 = I,
+ * T_1 = B, T_{k+1} = 2 B T_k - T_{k-1}, each T_k formed and accumulated.
+ * Returns 0 or -1.
+ */
+int orc_matfunc_cheb(int64_t n, const double *A, int64_t lda, double lo,
+                     double hi, const double *c, int ncoef, double *F,
+                     int64_t ldf)
+{
+    if (n < 1 || lda < n || ldf < n || ncoef < 1 || !c || !(hi > lo))
+        return -1;
+    const size_t nn = (size_t)(n * n);
+    double *B = (double *)malloc(sizeof(double) * nn);
+    double *Tp = (double *)malloc(sizeof(double) * nn);   /* T_{k-1} */
+    double *Tc = (double *)malloc(sizeof(double) * nn);   /* T_k */
+    double *Tn = (double *)malloc(sizeof(double) * nn);   /* T_{k+1} */
+    if (!B || !Tp || !Tc || !Tn) {
+        free(B); free(Tp); free(Tc); free(Tn);
+        return -1;
+    }
+    const double w = hi - lo;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            B[i * n + j] = (2.0 * A[i * lda + j] - (i == j ? lo + hi : 0.0)) / w;
+            Tp[i * n + j] = (i == j ? 1.0 : 0.0);
+            Tc[i * n + j] = B[i * n + j];
+            F[i * ldf + j] = c[0] * Tp[i * n + j];
+        }
+    if (ncoef > 1)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                F[i * ldf + j] += c[1] * Tc[i * n + j];
+    for (int k = 2; k < ncoef; ++k) {
+        orc_gemm(0, 0, n, n, n, 2.0, B, n, Tc, n, 0.0, Tn, n);
+        for (size_t e = 0; e < nn; ++e)
+            Tn[e] -= Tp[e];
+        double *t = Tp; Tp = Tc; Tc = Tn; Tn = t;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                F[i * ldf + j] += c[k] * Tc[i * n + j];
+    }
+    free(B); free(Tp); free(Tc); free(Tn);
+    return 0;
+}

@@ -391,6 +391,93 @@ def pin_inverse_scale_invariance(orc):
     assert np.max(np.abs(X1 - X2)) < 1e-15
 
 
+# --------------------------------------------------------------------------- matrix functions
+
+def pin_matfunc_odd_exact_construction(orc):
+    """eq. MatFunc: for A = Q diag(s) V^T the odd series acts on s alone."""
+    c = la_inputs.polar_case(40, 24, 1e-2, seeds=(180, 181, 182))
+    coef = np.array([1.25, -0.75, 0.5, -0.125])
+    F = orc.matfunc_odd(c.A64, coef)
+    f = sum(ck * c.s ** (2 * k + 1) for k, ck in enumerate(coef))
+    want = (c.Q * f[None, :]) @ c.V.T
+    assert np.max(np.abs(F - want)) < 1e-13
+
+
+def pin_matfunc_odd_vs_numpy_svd(orc):
+    A = la_inputs.gaussian((20, 20), 183).astype(np.float64)
+    Us, S, Vt = np.linalg.svd(A)
+    A = A / S[0]
+    S = S / S[0]
+    coef = np.array([0.3, 0.9, -0.4])
+    F = orc.matfunc_odd(A, coef)
+    f = coef[0] * S + coef[1] * S ** 3 + coef[2] * S ** 5
+    assert np.max(np.abs(F - (Us * f[None, :]) @ Vt)) < 1e-13
+    # one coefficient: c0 A exactly; [0, 1]: A (A^T A)
+    assert np.array_equal(orc.matfunc_odd(A, [2.0]), 2.0 * A)
+    assert np.max(np.abs(orc.matfunc_odd(A, [0.0, 1.0]) - A @ (A.T @ A))) < 1e-14
+
+
+def _cheb_values(lam, lo, hi, coef):
+    """sum_k c_k T_k(t) with T_k(cos th) = cos(k th), t = (2 lam - lo - hi) / (hi - lo)."""
+    t = np.clip((2.0 * lam - (lo + hi)) / (hi - lo), -1.0, 1.0)
+    th = np.arccos(t)
+    return sum(ck * np.cos(k * th) for k, ck in enumerate(coef))
+
+
+def pin_matfunc_cheb_symmetric_closed_form(orc):
+    """eq. MatFuncEig for A = V diag(lam) V^T: the series acts on lam alone."""
+    n = 30
+    V = la_inputs.haar(n, 184)
+    lam = np.linspace(-0.3, 2.0, n)
+    A = (V * lam[None, :]) @ V.T
+    lo, hi = -0.5, 2.5
+    coef = la_inputs.rng(185).standard_normal(11)
+    F = orc.matfunc_cheb(A, lo, hi, coef)
+    want = (V * _cheb_values(lam, lo, hi, coef)[None, :]) @ V.T
+    assert np.max(np.abs(F - want)) < 1e-12
+
+
+def pin_matfunc_cheb_nonsymmetric(orc):
+    """A = P diag(lam) P^-1 (diagonalisable, not symmetric): F = P g(lam) P^-1,
+    g evaluated with numpy's Chebyshev series routine."""
+    n = 16
+    P = np.eye(n) + 0.1 * la_inputs.gaussian((n, n), 186).astype(np.float64)
+    lam = np.linspace(0.1, 0.9, n)
+    A = P @ np.diag(lam) @ np.linalg.inv(P)
+    lo, hi = 0.0, 1.0
+    coef = np.array([0.5, -0.25, 0.125, 0.3, -0.2, 0.05])
+    g = np.polynomial.chebyshev.chebval((2 * lam - (lo + hi)) / (hi - lo), coef)
+    want = P @ np.diag(g) @ np.linalg.inv(P)
+    F = orc.matfunc_cheb(A, lo, hi, coef)
+    assert np.max(np.abs(F - want)) < 1e-12
+
+
+def pin_matfunc_cheb_low_degree(orc):
+    A = la_inputs.gaussian((12, 12), 187).astype(np.float64) * 0.1
+    lo, hi = -2.0, 3.0
+    B = (2 * A - (lo + hi) * np.eye(12)) / (hi - lo)
+    assert np.array_equal(orc.matfunc_cheb(A, lo, hi, [1.0]), np.eye(12))
+    assert np.max(np.abs(orc.matfunc_cheb(A, lo, hi, [0.0, 1.0]) - B)) < 1e-15
+    assert np.max(np.abs(orc.matfunc_cheb(A, lo, hi, [0.0, 0.0, 1.0]) -
+                         (2 * B @ B - np.eye(12)))) < 1e-14
+    assert np.max(np.abs(orc.matfunc_cheb(A, -1.0, 1.0, [0.0, 1.0]) - A)) < 1e-16
+
+
+def pin_matfunc_cheb_exponential(orc):
+    """A smooth function through its Chebyshev interpolant (numpy) against
+    scipy's matrix exponential, for a symmetric A with spectrum in [lo, hi]."""
+    import scipy.linalg
+    n = 24
+    V = la_inputs.haar(n, 188)
+    lam = la_inputs.rng(189).uniform(-1.0, 1.5, size=n)
+    A = (V * lam[None, :]) @ V.T
+    lo, hi = -1.0, 1.5
+    coef = np.polynomial.chebyshev.chebinterpolate(
+        lambda t: np.exp(0.5 * (t * (hi - lo) + lo + hi)), 20)
+    F = orc.matfunc_cheb(A, lo, hi, coef)
+    assert np.max(np.abs(F - scipy.linalg.expm(A))) < 1e-12
+
+
 ALL_PINS = [
     pin_paper_iteration_counts,
     pin_scalar_map_properties,
@@ -411,4 +498,10 @@ ALL_PINS = [
     pin_inverse_diagonal_closed_form,
     pin_inverse_orthogonal_stop_rule,
     pin_inverse_scale_invariance,
+    pin_matfunc_odd_exact_construction,
+    pin_matfunc_odd_vs_numpy_svd,
+    pin_matfunc_cheb_symmetric_closed_form,
+    pin_matfunc_cheb_nonsymmetric,
+    pin_matfunc_cheb_low_degree,
+    pin_matfunc_cheb_exponential,
 ]

@@ -42,6 +42,17 @@ MUTANTS = {
     "inv_delta_literal": ("const double scale = normalize ? sqrt(a) : 1.0;", "const double scale = 1.0;"),
     "inv_delta_sign": ("d2 += (Xn[i] - Xc[i]) * (Xn[i] - Xc[i]);", "d2 += (Xn[i] + Xc[i]) * (Xn[i] + Xc[i]);"),
     "inv_map_sign": ("return x * (2.0 - d * x);", "return x * (2.0 + d * x);"),
+    "odd_gram_transposed": ("orc_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, G, n);",
+                            "orc_gemm(0, 1, n, n, n, 1.0, A, lda, A, lda, 0.0, G, n);"),
+    "odd_coef_index": ("F[i * ldf + j] += c[p] * T[i * n + j];",
+                       "F[i * ldf + j] += c[p - 1] * T[i * n + j];"),
+    "cheb_recurrence_sign": ("Tn[e] -= Tp[e];", "Tn[e] += Tp[e];"),
+    "cheb_factor_two": ("orc_gemm(0, 0, n, n, n, 2.0, B, n, Tc, n, 0.0, Tn, n);",
+                        "orc_gemm(0, 0, n, n, n, 1.0, B, n, Tc, n, 0.0, Tn, n);"),
+    "cheb_affine_map": ("(2.0 * A[i * lda + j] - (i == j ? lo + hi : 0.0)) / w;",
+                        "(A[i * lda + j] - (i == j ? lo : 0.0)) / w;"),
+    "cheb_first_term": ("F[i * ldf + j] += c[1] * Tc[i * n + j];",
+                        "F[i * ldf + j] += c[1] * Tp[i * n + j];"),
 }
 
 
