@@ -209,6 +209,41 @@ def inverse_section(la, torch, n=16384, lo=1e-2, seeds=(601, 602, 603)):
     return out
 
 
+def matfunc_section(la, torch, n=8192, degree=16, seed=701):
+    """Chebyshev series of degree 16 (Clenshaw, 15 products) and a 5-term odd
+    singular-value series (Gram + 3 Horner products + final product) of an
+    n x n A, AUTO (6xBF16) and all-FP32-MFMA."""
+    import la_inputs
+
+    g = torch.Generator(device="cuda:0").manual_seed(seed)
+    A = torch.randn((n, n), device="cuda:0", generator=g) / (2.0 * n ** 0.5)
+    A = 0.5 * (A + A.T)                                   # symmetric, spectrum in ~[-1, 1]
+    F = torch.empty_like(A)
+    c = la_inputs.rng(seed).standard_normal(degree + 1)
+    c5 = [0.9, -0.6, 0.35, -0.2, 0.05]
+    ws = torch.empty(la.lib().la_matfunc_workspace_size(n, n) + 256, dtype=torch.uint8,
+                     device="cuda:0")
+    out = {"workload": f"Chebyshev series degree {degree} on [-1, 1] and 5-term odd series of a "
+                       f"{n}x{n} symmetric Gaussian A (seed {seed})"}
+    for name, prec in (("auto", la.Precision.AUTO), ("fp32", la.Precision.FP32)):
+        res = {}
+        for kind, fn, flops in (
+                ("cheb", lambda: la.matfunc_cheb(A, -1.0, 1.0, c, F=F, prec=prec, workspace=ws),
+                 2.0 * (degree - 1) * float(n) ** 3),
+                ("odd", lambda: la.matfunc_odd(A, c5, F=F, prec=prec, workspace=ws),
+                 (1.0 + 2.0 * (len(c5) - 2) + 2.0) * float(n) ** 3)):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            res[kind] = {"seconds": round(dt, 4), "tflops_algorithmic": round(flops / dt / 1e12, 1)}
+        out[name] = res
+        print(f"[bench] matfunc {name}: {res}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_pool(torch, pool_size=48, seed=401):
     """Pool of square polar inputs (n log-uniform in [128, 4096], cond 10^U(1,6))."""
     import la_inputs
@@ -321,6 +356,7 @@ def main():
     ap.add_argument("--no-tall", action="store_true", help="skip the 131072 x 4096 polar")
     ap.add_argument("--no-oracle-polar", action="store_true")
     ap.add_argument("--no-inverse", action="store_true")
+    ap.add_argument("--no-matfunc", action="store_true")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -436,6 +472,9 @@ def main():
             out["polar"]["cpu_oracle"] = oracle_polar_timing()
     if not args.no_inverse and args.only is None:
         out["inverse"] = inverse_section(la, torch)
+        torch.cuda.empty_cache()
+    if not args.no_matfunc and args.only is None:
+        out["matfunc"] = matfunc_section(la, torch)
         torch.cuda.empty_cache()
     if not args.no_serving and args.only is None:
         pool = serving_pool(torch)

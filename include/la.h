@@ -13,14 +13,17 @@
  *                (NewtonSchulz));
  *   la_inverse -- X with X A = I or A X = I for a full-rank (N, M) A, by the
  *                Newton-Schulz inversion of Algorithm NS_Inverse (III.D);
+ *   la_matfunc_odd / la_matfunc_cheb -- polynomial matrix functions of the
+ *                singular values (eq. OddPoly) and of the eigenvalues by a
+ *                Chebyshev series (eq. EigenvaluePolynomial, III.D);
  *   la_serve_* -- a continuous-batching server of la_polar requests.
  *
  * Conventions (the paper is silent on all of them):
  *   - real FP32 data, ROW-MAJOR with explicit leading dimensions: element
  *     (i, j) of X with leading dimension ldx is X[i * ldx + j];
- *   - every matrix pointer passed to la_gemm / la_polar / la_inverse is
- *     DEVICE memory owned by the caller; the library never frees or retains
- *     it;
+ *   - every matrix pointer passed to la_gemm / la_polar / la_inverse /
+ *     la_matfunc_* is DEVICE memory owned by the caller; the library never
+ *     frees or retains it;
  *   - hip_stream is a hipStream_t (NULL = the legacy default stream); la_gemm
  *     only enqueues work, la_polar and la_inverse block on a per-iteration
  *     8-byte readback;
@@ -60,7 +63,9 @@ typedef enum {
  *   BF16X6 : x = hi + mid + lo (three bf16 terms, 24 significant bits);
  *            products hh + hm + mh + mm + hl + lh.
  *   AUTO   : la_gemm -> BF16X3; la_polar -> per phase (see la_polar_opts):
- *            preconditioning and H at BF16X6, Newton-Schulz at BF16X3.
+ *            preconditioning and H at BF16X6, Newton-Schulz at BF16X3;
+ *            la_inverse -> BF16X3 steps and one BF16X6 step; la_matfunc_* ->
+ *            BF16X6.
  * The paper's TPU "fp32" matmul is itself a bf16-based emulation at about
  * six times the bf16 cost (section II); BF16X6 is the analogue here. */
 typedef enum {
@@ -201,6 +206,40 @@ size_t la_inverse_workspace_size(int64_t n, int64_t m, const la_inverse_opts *op
 la_status la_inverse(la_context *ctx, int64_t n, int64_t m, const float *A, int64_t lda,
                      float *X, int64_t ldx, void *workspace, size_t ws_bytes,
                      const la_inverse_opts *opts, la_inverse_info *info, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Polynomial matrix functions (section III.D, eqs. MatFunc-OddPoly and
+ * MatFuncEig-EigenvaluePolynomial).  coef is a HOST array of ncoef >= 1
+ * finite doubles (rounded to FP32 where they enter a product's epilogue).
+ * workspace: device memory of at least la_matfunc_workspace_size() bytes,
+ * 256-byte aligned (three n x n FP32 buffers).  prec: AUTO = BF16X6 (the
+ * recurrences accumulate the products' errors, so every product is kept at
+ * FP32-level accuracy).  Both run on hip_stream and return after the last
+ * kernel has completed.  F must not overlap A or the workspace.
+ * ---------------------------------------------------------------------- */
+size_t la_matfunc_workspace_size(int64_t m, int64_t n);
+
+/* Odd polynomial of the singular values of an m x n A (lda >= n):
+ *   F = sum_{j=0}^{ncoef-1} coef[j] A (A^T A)^j      (F m x n, ldf >= n),
+ * i.e. f(A) = U_s f(S) V_s^T for f(x) = coef[0] x + coef[1] x^3 + ...
+ * Evaluated as A p(A^T A) with Horner's rule in the Gram matrix: one
+ * symmetric Gram launch, ncoef - 2 products of n x n matrices and a final
+ * m x n product. */
+la_status la_matfunc_odd(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda,
+                         const double *coef, int ncoef, float *F, int64_t ldf, void *workspace,
+                         size_t ws_bytes, la_precision prec, void *hip_stream);
+
+/* Chebyshev series of the eigenvalues of an n x n A (lda >= n) on
+ * [lo, hi] (finite, lo < hi):
+ *   F = sum_{k=0}^{ncoef-1} coef[k] T_k(B),  B = (2A - (lo + hi) I) / (hi - lo)
+ * (coef[0] carries full weight; F n x n, ldf >= n).  Evaluated by
+ * Clenshaw's recurrence: ncoef - 2 GEMM launches for ncoef >= 3.  The
+ * series approximates g(A) when the eigenvalues of A lie in [lo, hi]; it is
+ * computed for any A. */
+la_status la_matfunc_cheb(la_context *ctx, int64_t n, const float *A, int64_t lda, double lo,
+                          double hi, const double *coef, int ncoef, float *F, int64_t ldf,
+                          void *workspace, size_t ws_bytes, la_precision prec,
+                          void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of polar requests.

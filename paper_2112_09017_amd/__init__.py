@@ -18,7 +18,8 @@ from ._binding import (InverseInfo, LAError, PolarInfo, PolarOpts, Precision, Se
                        LIB_PATH, SIGNATURES)
 
 __all__ = ["gemm", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
-           "Precision", "LAError", "Status", "lib", "LIB_PATH", "Server"]
+           "matfunc_odd", "matfunc_cheb", "Precision", "LAError", "Status", "lib", "LIB_PATH",
+           "Server"]
 
 
 def _stream_ptr(stream) -> ctypes.c_void_p:
@@ -142,6 +143,66 @@ def inverse(A: torch.Tensor, *, X: torch.Tensor | None = None,
         return X, info.as_dict()
     check(st)
     return X, info.as_dict()
+
+
+def _coef_array(coef):
+    import numpy as np
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).ravel())
+    return c, c.ctypes.data
+
+
+def _matfunc_workspace(workspace, m, n, dev):
+    need = int(lib().la_matfunc_workspace_size(m, n))
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wp = workspace.data_ptr()
+    wp_al = (wp + 255) & ~255
+    return workspace, wp_al, max(workspace.numel() - (wp_al - wp), 0)
+
+
+def matfunc_odd(A: torch.Tensor, coef, *, F: torch.Tensor | None = None,
+                prec: Precision = Precision.AUTO, workspace: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """F = sum_j coef[j] A (A^T A)^j through ``la_matfunc_odd`` (eq. OddPoly)."""
+    pa, m, n, lda, ta = _as_matrix(A, "A")
+    if ta:
+        A = A.contiguous()
+        pa, m, n, lda, ta = _as_matrix(A, "A")
+    if F is None:
+        F = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    pf, mf, nf, ldf, tf = _as_matrix(F, "F")
+    if (mf, nf) != (m, n) or tf:
+        raise ValueError("F must be a row-major m x n tensor")
+    c, cp = _coef_array(coef)
+    workspace, wp, avail = _matfunc_workspace(workspace, m, n, A.device)
+    ctx = context(A.device.index if A.device.index is not None else torch.cuda.current_device())
+    check(lib().la_matfunc_odd(ctx, m, n, pa, lda, cp, len(c), pf, ldf, wp, avail, int(prec),
+                               _stream_ptr(stream)))
+    return F
+
+
+def matfunc_cheb(A: torch.Tensor, lo: float, hi: float, coef, *, F: torch.Tensor | None = None,
+                 prec: Precision = Precision.AUTO, workspace: torch.Tensor | None = None,
+                 stream=None) -> torch.Tensor:
+    """F = sum_k coef[k] T_k((2A - (lo + hi) I) / (hi - lo)) through ``la_matfunc_cheb``
+    (eq. EigenvaluePolynomial, Clenshaw's recurrence)."""
+    pa, n, n2, lda, ta = _as_matrix(A, "A")
+    if ta:
+        A = A.contiguous()
+        pa, n, n2, lda, ta = _as_matrix(A, "A")
+    if n != n2:
+        raise ValueError("A must be square")
+    if F is None:
+        F = torch.empty((n, n), dtype=torch.float32, device=A.device)
+    pf, mf, nf, ldf, tf = _as_matrix(F, "F")
+    if (mf, nf) != (n, n) or tf:
+        raise ValueError("F must be a row-major n x n tensor")
+    c, cp = _coef_array(coef)
+    workspace, wp, avail = _matfunc_workspace(workspace, n, n, A.device)
+    ctx = context(A.device.index if A.device.index is not None else torch.cuda.current_device())
+    check(lib().la_matfunc_cheb(ctx, n, pa, lda, float(lo), float(hi), cp, len(c), pf, ldf, wp,
+                                avail, int(prec), _stream_ptr(stream)))
+    return F
 
 
 from .serve import Server  # noqa: E402

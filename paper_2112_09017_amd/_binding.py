@@ -142,6 +142,12 @@ SIGNATURES = {
     "la_inverse_workspace_size": (ctypes.c_size_t, [_I64, _I64, ctypes.POINTER(InverseOpts)]),
     "la_inverse": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, ctypes.c_size_t,
                                   ctypes.POINTER(InverseOpts), ctypes.POINTER(InverseInfo), _VP]),
+    "la_matfunc_workspace_size": (ctypes.c_size_t, [_I64, _I64]),
+    "la_matfunc_odd": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, ctypes.c_int, _VP, _I64,
+                                      _VP, ctypes.c_size_t, ctypes.c_int, _VP]),
+    "la_matfunc_cheb": (ctypes.c_int, [_VP, _I64, _VP, _I64, ctypes.c_double, ctypes.c_double,
+                                       _VP, ctypes.c_int, _VP, _I64, _VP, ctypes.c_size_t,
+                                       ctypes.c_int, _VP]),
     "la_serve_create": (ctypes.c_int, [_VP, ctypes.POINTER(ServeConfig), _VP, ctypes.c_size_t,
                                        ctypes.POINTER(_VP)]),
     "la_serve_submit": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, ctypes.POINTER(PolarOpts),

@@ -1,6 +1,7 @@
-// Auxiliary kernels of the polar driver: FP64 norm reductions (the scaling
-// ||A||_F and the step norm ||U' - U||_F of Algorithm NS_Polar, section
-// III.D), scaling, copies, symmetrisation of H, split-K reduction, and the
+// Auxiliary kernels of the polar, inversion and matrix-function drivers: FP64
+// norm reductions (the scaling ||A||_F and the step norm ||U' - U||_F of
+// Algorithm NS_Polar, section III.D), scaling, transpose-scaling, the affine
+// map s A + t I, copies, symmetrisation of H, split-K reduction, and the
 // precision dispatch of the GEMM launchers.
 #include <hip/hip_runtime.h>
 
@@ -191,6 +192,18 @@ __global__ void transpose_scale_kernel(const float *__restrict__ A, int64_t lda,
     }
 }
 
+// Y = s A + t I for an n x n A, in FP64 per element, rounded once (A is not
+// read when s == 0).
+__global__ void affine_kernel(const float *__restrict__ A, int64_t lda, float *__restrict__ Y,
+                              int64_t ldy, int64_t n, double sc, double t)
+{
+    for (int64_t r = blockIdx.y; r < n; r += gridDim.y)
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            Y[r * ldy + c] =
+                (float)((sc != 0.0 ? sc * (double)A[r * lda + c] : 0.0) + (r == c ? t : 0.0));
+}
+
 __global__ void copy_kernel(const float *__restrict__ X, int64_t ldx, float *__restrict__ Y,
                             int64_t ldy, int64_t m, int64_t n)
 {
@@ -292,6 +305,16 @@ hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t
     const unsigned gy = (unsigned)std::min<int64_t>(tm, 65535);
     hipLaunchKernelGGL(transpose_scale_kernel, dim3((unsigned)tn, gy), dim3(32, 8), 0, s, A, lda,
                        X, ldx, n, m, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_affine(const float *A, int64_t lda, float *Y, int64_t ldy, int64_t n,
+                         double sc, double t, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(affine_kernel, grid2d(n, n), dim3(kThreads), 0, s, A, lda, Y, ldy, n, sc,
+                       t);
     return hipGetLastError();
 }
 

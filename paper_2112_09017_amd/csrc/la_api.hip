@@ -36,20 +36,13 @@ void set_error(const char *fmt, ...)
     va_end(ap);
 }
 
-static la_status dev_fail(hipError_t e, const char *where)
+la_status dev_fail(hipError_t e, const char *where)
 {
     set_error("%s: %s", where, hipGetErrorString(e));
     return LA_ERR_DEVICE;
 }
 
-#define LA_HIP(call, where)                        \
-    do {                                           \
-        hipError_t e_ = (call);                    \
-        if (e_ != hipSuccess)                      \
-            return dev_fail(e_, where);            \
-    } while (0)
-
-static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 {
     if (!a || !b || abytes == 0 || bbytes == 0)
         return false;
@@ -57,19 +50,19 @@ static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
     return a0 < b0 + bbytes && b0 < a0 + abytes;
 }
 
-static size_t extent_bytes(int64_t rows, int64_t cols, int64_t ld)
+size_t extent_bytes(int64_t rows, int64_t cols, int64_t ld)
 {
     if (rows <= 0 || cols <= 0)
         return 0;
     return (size_t)((rows - 1) * ld + cols) * sizeof(float);
 }
 
-static int resolve(int p, int dflt)
+int resolve_prec(int p, int dflt)
 {
     return p == LA_PREC_AUTO ? dflt : p;
 }
 
-static bool valid_prec(int p)
+bool valid_prec(int p)
 {
     return p == LA_PREC_AUTO || p == LA_PREC_FP32 || p == LA_PREC_BF16X3 ||
            p == LA_PREC_BF16X6;
@@ -104,12 +97,12 @@ la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan 
         set_error("la_polar_opts: need 0 < s_minus < 1 and finite s0, eps");
         return LA_ERR_INVALID_ARG;
     }
-    p.prec_pre = resolve(o.prec_precond, PREC_BF16X6);
-    p.prec_ns = resolve(o.prec_ns, PREC_BF16X3);
+    p.prec_pre = resolve_prec(o.prec_precond, PREC_BF16X6);
+    p.prec_ns = resolve_prec(o.prec_ns, PREC_BF16X3);
     // H = sym(U^T A) is one product (about 2 of the ~85 N^3 of a polar) but its
     // error enters the residual directly: at 3xBF16 it alone is about
     // 2^-16 ||A||_F, so AUTO computes it at 6xBF16.
-    p.prec_h = resolve(o.prec_h, PREC_BF16X6);
+    p.prec_h = resolve_prec(o.prec_h, PREC_BF16X6);
     // eq. (a_def) and the recurrence of eq. (RogueScalar): the number of
     // preconditioning steps is fixed before any matrix work.
     p.a = 1.5 * sqrt(3.0) - p.s_minus;
@@ -137,7 +130,8 @@ int gram_splits(int64_t m, int64_t n, int prec)
     return (int)std::max<int64_t>(sp, 1);
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
+static size_t align256(size_t x) { return align_up256(x); }
 
 struct PolarWs {
     float *X;        // m x n, ld n: the iterate's second buffer
@@ -327,7 +321,7 @@ static la_status inverse_plan(int64_t n, int64_t m, const la_inverse_opts *opts,
     // accuracy.
     p.polish = o.polish != 0 || o.prec == LA_PREC_AUTO;
     p.literal = o.literal_delta != 0;
-    p.prec = resolve(o.prec, PREC_BF16X3);
+    p.prec = resolve_prec(o.prec, PREC_BF16X3);
     *out = p;
     return LA_OK;
 }
@@ -553,7 +547,7 @@ la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m, int64_t 
         return LA_ERR_INVALID_ARG;
     }
     LA_HIP(hipSetDevice(ctx->device), "la_gemm: hipSetDevice");
-    const int p = resolve(prec, PREC_BF16X3);
+    const int p = resolve_prec(prec, PREC_BF16X3);
     GemmDesc d;
     memset(&d, 0, sizeof d);
     d.A = A;

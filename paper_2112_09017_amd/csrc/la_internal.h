@@ -82,6 +82,9 @@ hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy,
 // X = A^T / a (FP64 division, rounded once); A is n x m, X is m x n.
 hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t ldx,
                                   int64_t n, int64_t m, double a, hipStream_t s);
+// Y = s A + t I for an n x n A (FP64 per element, rounded once).
+hipError_t launch_affine(const float *A, int64_t lda, float *Y, int64_t ldy, int64_t n,
+                         double sc, double t, hipStream_t s);
 // Y = X (strided copy).
 hipError_t launch_copy(const float *X, int64_t ldx, float *Y, int64_t ldy,
                        int64_t m, int64_t n, hipStream_t s);
@@ -118,5 +121,20 @@ size_t polar_workspace_bytes(const PolarPlan &p);
 
 // Thread-local error text.
 void set_error(const char *fmt, ...);
+
+// Argument helpers shared by the ABI entry points (la_api.hip).
+la_status dev_fail(hipError_t e, const char *where);   // sets the error, LA_ERR_DEVICE
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes);
+size_t extent_bytes(int64_t rows, int64_t cols, int64_t ld);   // bytes spanned by a matrix
+int resolve_prec(int p, int dflt);                      // AUTO -> dflt
+bool valid_prec(int p);
+size_t align_up256(size_t x);
+
+#define LA_HIP(call, where)                        \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess)                      \
+            return ::la::dev_fail(e_, where);      \
+    } while (0)
 
 }  // namespace la

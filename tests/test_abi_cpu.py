@@ -25,7 +25,8 @@ def L():
 def test_header_declares_expected_api():
     names = declared_functions()
     for n in ("la_create", "la_destroy", "la_gemm", "la_polar", "la_polar_workspace_size",
-              "la_inverse", "la_inverse_workspace_size", "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
+              "la_inverse", "la_inverse_workspace_size", "la_matfunc_odd", "la_matfunc_cheb",
+              "la_matfunc_workspace_size", "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
               "la_status_string", "la_last_error"):
         assert n in names
 
@@ -91,6 +92,30 @@ def test_inverse_argument_validation_without_device(L):
     assert L.la_inverse(None, 8, 6, None, 6, None, 7, None, 0, None, None, None) == 2
     assert L.la_inverse(None, 8, 6, None, 6, None, 8, None, 0, None, None, None) == 1
     assert L.la_last_error() == b"la_inverse: NULL argument"
+
+
+def test_matfunc_argument_validation_without_device(L):
+    import numpy as np
+    assert L.la_matfunc_workspace_size(0, 4) == 0
+    assert L.la_matfunc_workspace_size(300, 200) >= 3 * 4 * 200 * 200
+    c = np.array([1.0, 2.0])
+    cp = c.ctypes.data
+    # shape, coefficients, precision, then NULL arguments
+    assert L.la_matfunc_odd(None, 0, 4, None, 4, cp, 2, None, 4, None, 0, 0, None) == 2
+    assert L.la_matfunc_odd(None, 4, 4, None, 3, cp, 2, None, 4, None, 0, 0, None) == 2
+    assert L.la_matfunc_odd(None, 4, 4, None, 4, cp, 0, None, 4, None, 0, 0, None) == 1
+    assert L.la_matfunc_odd(None, 4, 4, None, 4, None, 2, None, 4, None, 0, 0, None) == 1
+    bad = np.array([1.0, np.nan])
+    assert L.la_matfunc_odd(None, 4, 4, None, 4, bad.ctypes.data, 2, None, 4, None, 0, 0,
+                            None) == 1
+    assert L.la_matfunc_odd(None, 4, 4, None, 4, cp, 2, None, 4, None, 0, 7, None) == 1
+    assert L.la_matfunc_odd(None, 4, 4, None, 4, cp, 2, None, 4, None, 0, 0, None) == 1
+    assert L.la_last_error() == b"la_matfunc_odd: NULL argument"
+    assert L.la_matfunc_cheb(None, 4, None, 4, 1.0, 1.0, cp, 2, None, 4, None, 0, 0, None) == 1
+    assert L.la_matfunc_cheb(None, 4, None, 4, 0.0, np.inf, cp, 2, None, 4, None, 0, 0,
+                             None) == 1
+    assert L.la_matfunc_cheb(None, 4, None, 2, 0.0, 1.0, cp, 2, None, 4, None, 0, 0, None) == 2
+    assert L.la_matfunc_cheb(None, 4, None, 4, 0.0, 1.0, cp, 2, None, 4, None, 0, 0, None) == 1
 
 
 def test_create_reports_missing_device(L):
