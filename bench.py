@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 M, N, K = 16384, 16384, 32768
 PEAK_BF16 = 2516.6      # TFLOP/s, dense BF16 MFMA, MI355X
 PEAK_FP32 = 157.3       # TFLOP/s, FP32 MFMA, MI355X
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_bf16x3_16384x16384x32768_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_packed_bf16x3_16384x16384x32768_traffic.json")
 KERNEL_SOURCES = ["paper_2112_09017_amd/csrc/gemm_tile.h", "paper_2112_09017_amd/csrc/gemm_x3.hip"]
 
 
@@ -403,19 +403,45 @@ def main():
 
     rates = {}
     precs = [args.only] if args.only else ["BF16X3", "FP32", "BF16X6"]
+    kernel_ms = None
     for p in precs:
         prec = getattr(la.Precision, p)
-        ms = time_launches(lambda: la.gemm(Ad, Bd, Cd, prec=prec),
-                           args.steps if p == precs[0] else max(2, args.steps // 3),
-                           args.warmup if p == precs[0] else 1, torch)
+        steps = args.steps if p == precs[0] else max(2, args.steps // 3)
+        warm = args.warmup if p == precs[0] else 1
+        if p == "BF16X3":
+            # the step: la_gemm_ws = pack op(A), pack op(B) (one HBM pass each) +
+            # the packed-operand GEMM kernel
+            ws = torch.empty(la.gemm_workspace_size(M, N, K) + 256, dtype=torch.uint8,
+                             device=dev)
+            ms = time_launches(lambda: la.gemm_ws(Ad, Bd, Cd, prec=prec, workspace=ws), steps,
+                               warm, torch)
+            # the GEMM kernel alone, on operands packed once
+            Ap = la.pack_bf16x3(Ad)
+            Bp = la.pack_bf16x3(Bd.T)
+            kernel_ms = time_launches(lambda: la.gemm_packed(Ap, Bp, M, N, K, Cd), steps, 1,
+                                      torch)
+            del Ap, Bp, ws
+            torch.cuda.empty_cache()
+            # the unpacked kernel (la_gemm), for comparison
+            ums = time_launches(lambda: la.gemm(Ad, Bd, Cd, prec=prec), max(2, steps // 3), 1,
+                                torch)
+            rates["BF16X3_unpacked"] = (ums, flops / ums / 1e9)
+            print(f"[bench] BF16X3 la_gemm (unpacked): {ums:.2f} ms, {flops / ums / 1e9:.1f} "
+                  f"TFLOP/s; packed kernel alone {kernel_ms:.2f} ms", file=sys.stderr, flush=True)
+        else:
+            ms = time_launches(lambda: la.gemm(Ad, Bd, Cd, prec=prec), steps, warm, torch)
         rates[p] = (ms, flops / ms / 1e9)
         print(f"[bench] {p}: {ms:.2f} ms/step, {rates[p][1]:.1f} TFLOP/s", file=sys.stderr,
               flush=True)
     head = precs[0]
     ms, tflops = rates[head]
+    kernel_tflops = flops / kernel_ms / 1e9 if kernel_ms else tflops
 
     # headline result for the baseline check (recompute, untimed)
-    la.gemm(Ad, Bd, Cd, prec=getattr(la.Precision, head))
+    if head == "BF16X3":
+        la.gemm_ws(Ad, Bd, Cd, prec=la.Precision.BF16X3)
+    else:
+        la.gemm(Ad, Bd, Cd, prec=getattr(la.Precision, head))
     torch.cuda.synchronize()
 
     ceiling = PEAK_BF16 / 3.0 if head == "BF16X3" else (
@@ -436,13 +462,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "block GEMM C=A*B, A 16384x32768, B 32768x16384, FP32 "
                                "entries N(0,1) seeds 201/202",
-                   "m": M, "n": N, "k": K, "precision": head},
+                   "m": M, "n": N, "k": K, "precision": head,
+                   "step": ("la_gemm_ws: pack op(A) and op(B) into bf16 hi/lo tiles, then "
+                            "the packed-operand GEMM") if head == "BF16X3" else "la_gemm"},
         "roofline": {
             "bound": "mfma",
-            "achieved": round(tflops, 2),
+            "kernel": ("la::dev::gemm_packed_kernel<34> (3xBF16 on packed operands, "
+                       "256x256 tiles)") if head == "BF16X3" else f"la::dev::gemm_kernel ({head})",
+            "achieved": round(kernel_tflops, 2),
             "peak": round(ceiling, 1),
             "unit": "TFLOP/s",
-            "frac": round(tflops / ceiling, 4),
+            "frac": round(kernel_tflops / ceiling, 4),
+            "kernel_ms": round(kernel_ms, 3) if kernel_ms else round(ms, 3),
             "traffic": traffic,
             "peak_basis": ("BF16 dense MFMA 2516.6 TFLOP/s / 3 BF16 products per FP32-accurate "
                            "multiply-add" if head == "BF16X3" else

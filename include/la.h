@@ -105,6 +105,37 @@ la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m,
                   int64_t lda, const float *B, int64_t ldb, float beta,
                   float *C, int64_t ldc, la_precision prec, void *hip_stream);
 
+/* Workspace variant of la_gemm (same arguments, same result bit for bit).
+ * When the product runs at BF16X3 (prec BF16X3 or AUTO) on 256 x 256 tiles
+ * with k >= 256, op(A) and op(B) are first split into their bf16 terms and
+ * written to `workspace` in the order the GEMM's LDS tiles use (one HBM pass
+ * over each operand), and the product then streams them straight from HBM to
+ * LDS, with no split in its inner loop.  Otherwise it runs exactly as
+ * la_gemm and does not touch the workspace.  workspace: device memory of at
+ * least la_gemm_workspace_size(m, n, k) bytes, 256-byte aligned, overlapping
+ * none of A, B, C.  Enqueued on hip_stream; returns without waiting. */
+size_t la_gemm_workspace_size(int64_t m, int64_t n, int64_t k);
+la_status la_gemm_ws(la_context *ctx, int trans_a, int trans_b, int64_t m,
+                     int64_t n, int64_t k, float alpha, const float *A,
+                     int64_t lda, const float *B, int64_t ldb, float beta,
+                     float *C, int64_t ldc, la_precision prec, void *workspace,
+                     size_t ws_bytes, void *hip_stream);
+
+/* The two halves of la_gemm_ws, for callers that reuse an operand (pack it
+ * once, multiply many times).  la_pack_bf16x3 splits op(X) (rows x k; kc = 1:
+ * element (r, p) is X[r * ld + p], kc = 0: X[p * ld + r]) into its bf16
+ * hi/lo terms in the GEMM's LDS tile order, zero-padded; `packed` is device
+ * memory of at least la_pack_size(rows, k) bytes.  la_gemm_packed computes
+ * C <- alpha op(A) op(B) + beta C from Ap = pack of op(A) (m x k) and Bp =
+ * pack of op(B)^T (n x k), bitwise as la_gemm at BF16X3 would.  Both are
+ * enqueued on hip_stream and return without waiting. */
+size_t la_pack_size(int64_t rows, int64_t k);
+la_status la_pack_bf16x3(la_context *ctx, int kc, int64_t rows, int64_t k, const float *X,
+                         int64_t ld, void *packed, size_t packed_bytes, void *hip_stream);
+la_status la_gemm_packed(la_context *ctx, int64_t m, int64_t n, int64_t k, float alpha,
+                         const void *Ap, const void *Bp, float beta, float *C, int64_t ldc,
+                         void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Polar factorisation (section III.D, Algorithm NS_Polar).
  * ---------------------------------------------------------------------- */

@@ -17,7 +17,7 @@ from ._binding import (InverseInfo, LAError, PolarInfo, PolarOpts, Precision, Se
                        ServeStats, Status, check, context, lib, make_inverse_opts, make_opts,
                        LIB_PATH, SIGNATURES)
 
-__all__ = ["gemm", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
+__all__ = ["gemm", "gemm_ws", "gemm_workspace_size", "pack_bf16x3", "gemm_packed", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
            "matfunc_odd", "matfunc_cheb", "Precision", "LAError", "Status", "lib", "LIB_PATH",
            "Server"]
 
@@ -56,6 +56,68 @@ def gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *, alp
     ctx = context(A.device.index if A.device.index is not None else torch.cuda.current_device())
     check(lib().la_gemm(ctx, int(ta), int(tb), m, n, k, float(alpha), pa, lda, pb, ldb,
                         float(beta), pc, ldc, int(prec), _stream_ptr(stream)))
+    return C
+
+
+def gemm_workspace_size(m: int, n: int, k: int) -> int:
+    return int(lib().la_gemm_workspace_size(m, n, k))
+
+
+def gemm_ws(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, *,
+            alpha: float = 1.0, beta: float = 0.0, prec: Precision = Precision.BF16X3,
+            workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """C <- alpha A @ B + beta C through ``la_gemm_ws`` (packed 3xBF16 operands
+    for large products; the same result as ``gemm``)."""
+    pa, m, k, lda, ta = _as_matrix(A, "A")
+    pb, k2, n, ldb, tb = _as_matrix(B, "B")
+    if k != k2:
+        raise ValueError(f"inner dimensions differ: {k} vs {k2}")
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float32, device=A.device)
+        beta = 0.0
+    pc, mc, nc, ldc, tc = _as_matrix(C, "C")
+    if (mc, nc) != (m, n) or tc:
+        raise ValueError("C must be a row-major m x n tensor")
+    if workspace is None:
+        workspace = torch.empty(gemm_workspace_size(m, n, k) + 256, dtype=torch.uint8,
+                                device=A.device)
+    wp = workspace.data_ptr()
+    wp_al = (wp + 255) & ~255
+    avail = max(workspace.numel() - (wp_al - wp), 0)
+    ctx = context(A.device.index if A.device.index is not None else torch.cuda.current_device())
+    check(lib().la_gemm_ws(ctx, int(ta), int(tb), m, n, k, float(alpha), pa, lda, pb, ldb,
+                           float(beta), pc, ldc, int(prec), wp_al, avail, _stream_ptr(stream)))
+    return C
+
+
+def pack_bf16x3(X: torch.Tensor, *, out: torch.Tensor | None = None, stream=None):
+    """Pack op(X) (rows x k, with X or X.T passed) through ``la_pack_bf16x3``:
+    returns a uint8 device tensor usable by ``gemm_packed``."""
+    px, r, c, ld, tx = _as_matrix(X, "X")
+    # a row-major tensor is op(X) with k contiguous; a transposed view has rows contiguous
+    need = int(lib().la_pack_size(r, c))
+    if out is None:
+        out = torch.empty(max(need, 1), dtype=torch.uint8, device=X.device)
+    ctx = context(X.device.index if X.device.index is not None else torch.cuda.current_device())
+    check(lib().la_pack_bf16x3(ctx, 0 if tx else 1, r, c, px, ld, out.data_ptr(), out.numel(),
+                               _stream_ptr(stream)))
+    return out
+
+
+def gemm_packed(Ap: torch.Tensor, Bp: torch.Tensor, m: int, n: int, k: int,
+                C: torch.Tensor | None = None, *, alpha: float = 1.0, beta: float = 0.0,
+                stream=None) -> torch.Tensor:
+    """C <- alpha op(A) op(B) + beta C from packed op(A) (m x k) and packed op(B)^T
+    (n x k) through ``la_gemm_packed``."""
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float32, device=Ap.device)
+        beta = 0.0
+    pc, mc, nc, ldc, tc = _as_matrix(C, "C")
+    if (mc, nc) != (m, n) or tc:
+        raise ValueError("C must be a row-major m x n tensor")
+    ctx = context(Ap.device.index if Ap.device.index is not None else torch.cuda.current_device())
+    check(lib().la_gemm_packed(ctx, m, n, k, float(alpha), Ap.data_ptr(), Bp.data_ptr(),
+                               float(beta), pc, ldc, _stream_ptr(stream)))
     return C
 
 

@@ -135,6 +135,15 @@ SIGNATURES = {
     "la_gemm": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I64, _I64, _I64, ctypes.c_float,
                                _VP, _I64, _VP, _I64, ctypes.c_float, _VP, _I64, ctypes.c_int,
                                _VP]),
+    "la_gemm_workspace_size": (ctypes.c_size_t, [_I64, _I64, _I64]),
+    "la_gemm_ws": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I64, _I64, _I64,
+                                  ctypes.c_float, _VP, _I64, _VP, _I64, ctypes.c_float, _VP, _I64,
+                                  ctypes.c_int, _VP, ctypes.c_size_t, _VP]),
+    "la_pack_size": (ctypes.c_size_t, [_I64, _I64]),
+    "la_pack_bf16x3": (ctypes.c_int, [_VP, ctypes.c_int, _I64, _I64, _VP, _I64, _VP,
+                                      ctypes.c_size_t, _VP]),
+    "la_gemm_packed": (ctypes.c_int, [_VP, _I64, _I64, _I64, ctypes.c_float, _VP, _VP,
+                                      ctypes.c_float, _VP, _I64, _VP]),
     "la_polar_workspace_size": (ctypes.c_size_t, [_I64, _I64, ctypes.POINTER(PolarOpts)]),
     "la_polar": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
                                 ctypes.c_size_t, ctypes.POINTER(PolarOpts),

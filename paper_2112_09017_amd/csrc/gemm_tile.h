@@ -84,6 +84,17 @@ template <> struct Cfg<PREC_BF16X6 | kSmall> {
     static constexpr int terms = 3, entry_bytes = 16;
 };
 
+// Packed 3xBF16 operands (kPacked): the operands were split into bf16 terms
+// and laid out in the LDS fragment order by a pack pass, so the K loop moves
+// them with direct global -> LDS loads; one 16-k block per stage, four LDS
+// stages in flight.
+constexpr int kPacked = 32;
+constexpr int kPackStages = 4;
+template <> struct Cfg<PREC_BF16X3 | kPacked> {
+    static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 0, GOCC = 1;
+    static constexpr int terms = 2, entry_bytes = 16;
+};
+
 template <int PREC> struct Geo {
     using C = Cfg<PREC>;
     static constexpr int NT = C::WM * C::WN * 64;
@@ -975,6 +986,269 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
     }
 }
 
+// ---------------------------------------------------------------- packed operands
+
+// Packed layout of an R x K operand op(X) (R = output rows for A, output
+// columns for B), written by pack_x3_kernel and read by gemm_packed_kernel:
+// 1 KiB chunks, chunk (rb, kb, t) at byte ((rb * KB + kb) * 2 + t) * 1024,
+// rb = block of 32 rows, kb = block of 16 k, t = term (0 hi, 1 lo).  Inside
+// a chunk, the 16 bytes of lane l hold the 8 bf16 of row 32 rb + (l & 31),
+// k = 16 kb + 8 (l >> 5) .. + 7: exactly one fragment block of the LDS image
+// (entry_off with KF = 1).  Rows are padded with zeros to a multiple of 256,
+// k to a multiple of 16, so the GEMM needs no bounds checks.
+constexpr int kPackRows = 256;
+constexpr int kPackSlabK = 128;   // k covered by one workgroup of the pack kernel
+
+template <bool KC>
+__global__ void __launch_bounds__(256) pack_x3_kernel(const float *__restrict__ X, int64_t ld,
+                                                      int64_t R, int64_t K, int64_t kbt,
+                                                      int64_t rbt, char *__restrict__ out)
+{
+    __shared__ float tile[32][kPackSlabK + 1];
+    const int t = threadIdx.x;
+    for (int64_t rb = blockIdx.y; rb < rbt; rb += gridDim.y) {
+        const int64_t r0 = rb * 32, k0 = (int64_t)blockIdx.x * kPackSlabK;
+        // stage 32 rows x 128 k through LDS (consecutive threads read
+        // consecutive addresses in either storage order); zero outside R x K
+#pragma unroll 4
+        for (int i = t; i < 32 * kPackSlabK; i += 256) {
+            int r, k;
+            if (KC) {
+                r = i / kPackSlabK;
+                k = i % kPackSlabK;
+            } else {
+                k = i / 32;
+                r = i % 32;
+            }
+            const int64_t gr = r0 + r, gk = k0 + k;
+            float v = 0.0f;
+            if (gr < R && gk < K)
+                v = KC ? X[gr * ld + gk] : X[gk * ld + gr];
+            tile[r][k] = v;
+        }
+        __syncthreads();
+        // 8 k blocks x 64 lane entries per term; two entries per thread
+        for (int e = t; e < (kPackSlabK / 16) * 64; e += 256) {
+            const int kbl = e >> 6, lane = e & 63;
+            const int64_t kb = (int64_t)blockIdx.x * (kPackSlabK / 16) + kbl;
+            if (kb >= kbt)
+                continue;
+            const int r = lane & 31, kk = kbl * 16 + (lane >> 5) * 8;
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = tile[r][kk + j];
+            u32x4 parts[2];
+            Split<PREC_BF16X3>::run(v, parts);
+            char *chunk = out + (((rb * kbt + kb) * 2) << 10);
+            *reinterpret_cast<u32x4 *>(chunk + lane * 16) = parts[0];
+            *reinterpret_cast<u32x4 *>(chunk + 1024 + lane * 16) = parts[1];
+        }
+        __syncthreads();
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// One 16-byte-per-lane global -> LDS load: lane l's 16 bytes at base + voff
+// go to LDS byte lds + 16 l.  Written as an asm statement so that the
+// compiler does not treat the pending LDS writes as aliasing every later LDS
+// read (it would drain all loads in flight before each stage); the K loop
+// waits for exactly the stages it needs with wait_vmcnt.  The compiler
+// writes M0 (the LDS base, wave-uniform); s_nop 0 is the one wait state an
+// M0 write needs before an LDS-DMA load.  The load has no register result.
+__device__ __forceinline__ void dma16(const void *base, uint32_t voff, uint32_t lds)
+{
+    // base: wave-uniform 64-bit address (SGPR pair); voff: per-lane byte offset
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "{m0}"(lds)
+                 : "memory");
+}
+
+__device__ __forceinline__ uint32_t lds_offset(const void *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const void *)p;
+}
+
+// Direct global -> LDS loads of one packed stage (k block kb): 16 chunks of
+// A (2 terms x 8 row blocks) and 16 of B.  Wave w moves operand (w >= 2 ? B
+// : A), term (w & 1), row blocks 0..7: eight 1 KiB chunks, each one
+// global_load_lds_dwordx4.  stage_lds: LDS byte offset of the stage buffer.
+template <int P>
+__device__ __forceinline__ void packed_issue(const char *pa, const char *pb, int64_t kbt,
+                                             int64_t rba, int64_t rbb, int64_t kb,
+                                             uint32_t stage_lds, int w, int lane)
+{
+    using G = Geo<P>;
+    const bool isb = w >= 2;
+    const char *base = isb ? pb : pa;
+    const int64_t rb0 = isb ? rbb : rba;
+    const uint32_t dst0 = stage_lds + (isb ? G::a_bytes : 0);
+    const int tt = w & 1;
+    const uint64_t wb = (uint64_t)(base + (((rb0 * kbt + kb) * 2 + tt) << 10));
+    const char *wbase = (const char *)(
+        ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(wb >> 32)) << 32) |
+        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wb));
+    const int64_t rb_stride = kbt << 11;   // bytes between consecutive row blocks
+#pragma unroll
+    for (int frow = 0; frow < 8; ++frow)
+        dma16(wbase + frow * rb_stride, lane * 16, dst0 + ((tt * 8 + frow) << 10));
+}
+
+// Fragments of one packed stage for this wave, in two halves: the operands
+// of the first product lo*hi (A lo, B hi) and the rest (A hi, B lo).
+template <int P>
+__device__ __forceinline__ void packed_read_first(const char *st, bf16x8 (&alo)[Geo<P>::FM],
+                                                  bf16x8 (&bhi)[Geo<P>::FN], int wm, int wn,
+                                                  int lane)
+{
+    using C = Cfg<P>;
+    using G = Geo<P>;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+        alo[i] = *reinterpret_cast<const bf16x8 *>(st + frag_off<C::BM, 1, 16>(1, wm * G::FM + i, 0, lane));
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+        bhi[j] = *reinterpret_cast<const bf16x8 *>(st + G::a_bytes +
+                                                   frag_off<C::BN, 1, 16>(0, wn * G::FN + j, 0, lane));
+}
+
+template <int P>
+__device__ __forceinline__ void packed_read_rest(const char *st, bf16x8 (&ahi)[Geo<P>::FM],
+                                                 bf16x8 (&blo)[Geo<P>::FN], int wm, int wn,
+                                                 int lane)
+{
+    using C = Cfg<P>;
+    using G = Geo<P>;
+#pragma unroll
+    for (int i = 0; i < G::FM; ++i)
+        ahi[i] = *reinterpret_cast<const bf16x8 *>(st + frag_off<C::BM, 1, 16>(0, wm * G::FM + i, 0, lane));
+#pragma unroll
+    for (int j = 0; j < G::FN; ++j)
+        blo[j] = *reinterpret_cast<const bf16x8 *>(st + G::a_bytes +
+                                                   frag_off<C::BN, 1, 16>(1, wn * G::FN + j, 0, lane));
+}
+
+// Wait until this wave's chunks of the next stage have landed, given how
+// many later stages (0..3, eight chunks each) may stay in flight.
+__device__ __forceinline__ void packed_wait(int later)
+{
+    if (later >= 3)
+        wait_vmcnt<24>();
+    else if (later == 2)
+        wait_vmcnt<16>();
+    else if (later == 1)
+        wait_vmcnt<8>();
+    else
+        wait_vmcnt<0>();
+}
+
+// One 16-k stage.  alo / bhi hold this stage's first-product fragments on
+// entry and the next stage's on exit.  The rest of this stage's fragments
+// are read while the lo*hi MFMAs run; after the hi*lo MFMAs (alo is dead
+// from here), wait for stage s+1, barrier, start the loads of stage s+4 into
+// this stage's buffer (every wave has consumed it) and read stage s+1's A lo
+// fragments; the hi*hi MFMAs run column by column, each B hi fragment
+// replaced by stage s+1's once its column is done.  Every accumulator sees
+// the products in the same order as in the unpacked 3xBF16 kernel.
+template <int P>
+__device__ __forceinline__ void packed_stage(int ss, int nst, f32x16 (&acc)[Geo<P>::FM][Geo<P>::FN],
+                                             bf16x8 (&alo)[Geo<P>::FM], bf16x8 (&bhi)[Geo<P>::FN],
+                                             const char *smem, uint32_t smem_lds, const char *pa,
+                                             const char *pb, int64_t kbt, int64_t rba, int64_t rbb,
+                                             int w, int wm, int wn, int lane)
+{
+    using C = Cfg<P>;
+    using G = Geo<P>;
+    constexpr int FM = G::FM, FN = G::FN, NS = kPackStages;
+    bf16x8 ahi[FM], blo[FN];
+    packed_read_rest<P>(smem + (ss & (NS - 1)) * G::stage_bytes, ahi, blo, wm, wn, lane);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[i], bhi[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[i], blo[j], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    const bool more = ss + 1 < nst;
+    const char *nst_ = smem + ((ss + 1) & (NS - 1)) * G::stage_bytes;
+    if (more) {
+        packed_wait(min(nst - 2 - ss, NS - 2));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        if (ss + NS < nst)
+            packed_issue<P>(pa, pb, kbt, rba, rbb, ss + NS, smem_lds + (ss & (NS - 1)) * G::stage_bytes,
+                            w, lane);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            alo[i] = *reinterpret_cast<const bf16x8 *>(nst_ + frag_off<C::BM, 1, 16>(1, wm * FM + i, 0, lane));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[i], bhi[j], acc[i][j], 0, 0, 0);
+        if (more)
+            bhi[j] = *reinterpret_cast<const bf16x8 *>(nst_ + G::a_bytes +
+                                                       frag_off<C::BN, 1, 16>(0, wn * FN + j, 0, lane));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// GEMM on packed operands: d.A / d.B point at the packed buffers, d.K is
+// the (unpadded) inner dimension; the epilogue is the common one.
+template <int P>
+__global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
+{
+    using G = Geo<P>;
+    static_assert(G::KF == 1 && G::NT == 256, "one 16-k block per stage, four waves");
+    constexpr int FM = G::FM, FN = G::FN, NS = kPackStages;
+    __shared__ __attribute__((aligned(1024))) char smem[NS * G::stage_bytes];
+    __shared__ double red[4];
+    const int lin = xcd_remap(blockIdx.x, d.num_tiles);
+    int tm, tn;
+    tile_coords(d, lin, tm, tn);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w / 2, wn = w % 2;
+    f32x16 acc[FM][FN];
+#pragma clang loop unroll(full)
+    for (int i = 0; i < FM; ++i)
+#pragma clang loop unroll(full)
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = f32x16{};
+    const char *pa = reinterpret_cast<const char *>(d.A);
+    const char *pb = reinterpret_cast<const char *>(d.B);
+    const int64_t kbt = (d.K + 15) / 16;
+    const int64_t rba = (int64_t)tm * 8, rbb = (int64_t)tn * 8;
+    const int nst = (int)kbt;
+    const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_offset(smem));
+    // first-product fragments of the current stage
+    bf16x8 alo[FM], bhi[FN];
+    if (nst > 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (s < nst)
+                packed_issue<P>(pa, pb, kbt, rba, rbb, s, smem_lds + s * G::stage_bytes, w, lane);
+        packed_wait(min(nst - 1, NS - 1));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        packed_read_first<P>(smem, alo, bhi, wm, wn, lane);
+    }
+    for (int s = 0; s < nst; ++s)
+        packed_stage<P>(s, nst, acc, alo, bhi, smem, smem_lds, pa, pb, kbt, rba, rbb, w, wm, wn,
+                        lane);
+    epilogue<P>(d, acc, tm, tn, wm, wn, lane, red);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int PREC>
@@ -1031,6 +1305,43 @@ hipError_t launch_grouped_t(int akc, int bkc, int small, const GemmDesc *probs,
     return small ? launch_grouped_one<PREC | kSmall>(akc, bkc, probs, items, num_items,
                                                      grid_size, s)
                  : launch_grouped_one<PREC>(akc, bkc, probs, items, num_items, grid_size, s);
+}
+
+// Packed operand bytes for R rows and inner dimension K.
+inline size_t packed_bytes(int64_t R, int64_t K)
+{
+    const int64_t rbt = (R + kPackRows - 1) / kPackRows * (kPackRows / 32);
+    const int64_t kbt = (K + 15) / 16;
+    return (size_t)rbt * (size_t)kbt * 2048;
+}
+
+inline hipError_t launch_pack_x3(const float *X, int64_t ld, int kc, int64_t R, int64_t K,
+                                 char *out, hipStream_t s)
+{
+    const int64_t rbt = (R + kPackRows - 1) / kPackRows * (kPackRows / 32);
+    const int64_t kbt = (K + 15) / 16;
+    if (rbt == 0 || kbt == 0)
+        return hipSuccess;
+    const int64_t gx = (kbt * 16 + kPackSlabK - 1) / kPackSlabK;
+    if (gx > 0x7fffffff)
+        return hipErrorInvalidValue;
+    const unsigned gy = (unsigned)(rbt < 65535 ? rbt : 65535);
+    if (kc)
+        hipLaunchKernelGGL((pack_x3_kernel<true>), dim3((unsigned)gx, gy), dim3(256), 0, s, X, ld,
+                           R, K, kbt, rbt, out);
+    else
+        hipLaunchKernelGGL((pack_x3_kernel<false>), dim3((unsigned)gx, gy), dim3(256), 0, s, X, ld,
+                           R, K, kbt, rbt, out);
+    return hipGetLastError();
+}
+
+inline hipError_t launch_packed_x3(const GemmDesc &d, hipStream_t s)
+{
+    if (d.num_tiles <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((gemm_packed_kernel<PREC_BF16X3 | kPacked>), dim3(d.num_tiles), dim3(256),
+                       0, s, d);
+    return hipGetLastError();
 }
 
 }  // namespace dev

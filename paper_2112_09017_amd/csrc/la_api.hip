@@ -441,6 +441,74 @@ static hipError_t inverse_step(const InvPlan &p, int prec, const float *A, int64
     return launch_gemm(prec, u, s);
 }
 
+// Validation and descriptor of a la_gemm-style call.  *empty: nothing to do
+// (m or n is 0) after successful validation.
+static la_status gemm_prepare(const char *who, la_context *ctx, int trans_a, int trans_b,
+                              int64_t m, int64_t n, int64_t k, float alpha, const float *A,
+                              int64_t lda, const float *B, int64_t ldb, float beta, float *C,
+                              int64_t ldc, int prec, GemmDesc *out, int *prec_out, bool *empty)
+{
+    *empty = false;
+    if (!valid_prec(prec)) {
+        set_error("%s: invalid precision %d", who, prec);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (m < 0 || n < 0 || k < 0) {
+        set_error("%s: negative size", who);
+        return LA_ERR_SHAPE;
+    }
+    const int64_t a_cols = trans_a ? m : k, a_rows = trans_a ? k : m;
+    const int64_t b_cols = trans_b ? k : n, b_rows = trans_b ? n : k;
+    if (lda < std::max<int64_t>(a_cols, 1) || ldb < std::max<int64_t>(b_cols, 1) ||
+        ldc < std::max<int64_t>(n, 1)) {
+        set_error("%s: leading dimension smaller than the row length", who);
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx) {
+        set_error("%s: ctx is NULL", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (m == 0 || n == 0) {
+        *empty = true;
+        return LA_OK;
+    }
+    if (!C || (k > 0 && (!A || !B))) {
+        set_error("%s: NULL matrix pointer", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t cb = extent_bytes(m, n, ldc);
+    if (k > 0 && (overlaps(C, cb, A, extent_bytes(a_rows, a_cols, lda)) ||
+                  overlaps(C, cb, B, extent_bytes(b_rows, b_cols, ldb)))) {
+        set_error("%s: C overlaps A or B", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_gemm: hipSetDevice");
+    const int p = resolve_prec(prec, PREC_BF16X3);
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.A = A;
+    d.lda = lda;
+    d.a_kcontig = trans_a ? 0 : 1;
+    d.B = B;
+    d.ldb = ldb;
+    d.b_kcontig = trans_b ? 1 : 0;
+    d.C = C;
+    d.ldc = ldc;
+    d.M = m;
+    d.N = n;
+    d.K = k;
+    d.alpha = alpha;
+    if (beta != 0.0f) {
+        d.E = C;
+        d.lde = ldc;
+        d.beta = beta;
+    }
+    gemm_finalize(d, p);
+    *out = d;
+    *prec_out = p;
+    return LA_OK;
+}
+
 }  // namespace la
 
 using namespace la;
@@ -515,47 +583,84 @@ la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m, int64_t 
                   float beta, float *C, int64_t ldc, la_precision prec, void *hip_stream)
 {
     g_err[0] = 0;
-    if (!valid_prec(prec)) {
-        set_error("la_gemm: invalid precision %d", (int)prec);
-        return LA_ERR_INVALID_ARG;
-    }
-    if (m < 0 || n < 0 || k < 0) {
-        set_error("la_gemm: negative size");
+    GemmDesc d;
+    int p = 0;
+    bool empty = false;
+    la_status st = gemm_prepare("la_gemm", ctx, trans_a, trans_b, m, n, k, alpha, A, lda, B, ldb,
+                                beta, C, ldc, prec, &d, &p, &empty);
+    if (st != LA_OK || empty)
+        return st;
+    LA_HIP(launch_gemm(p, d, (hipStream_t)hip_stream), "la_gemm: launch");
+    return LA_OK;
+}
+
+size_t la_pack_size(int64_t rows, int64_t k)
+{
+    if (rows < 0 || k < 0)
+        return 0;
+    return packed_x3_bytes(rows, k);
+}
+
+la_status la_pack_bf16x3(la_context *ctx, int kc, int64_t rows, int64_t k, const float *X,
+                         int64_t ld, void *packed, size_t packed_bytes, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (rows < 0 || k < 0 || ld < std::max<int64_t>(kc ? k : rows, 1)) {
+        set_error("la_pack_bf16x3: bad shape (rows %lld, k %lld, ld %lld)", (long long)rows,
+                  (long long)k, (long long)ld);
         return LA_ERR_SHAPE;
     }
-    const int64_t a_cols = trans_a ? m : k, a_rows = trans_a ? k : m;
-    const int64_t b_cols = trans_b ? k : n, b_rows = trans_b ? n : k;
-    if (lda < std::max<int64_t>(a_cols, 1) || ldb < std::max<int64_t>(b_cols, 1) ||
-        ldc < std::max<int64_t>(n, 1)) {
-        set_error("la_gemm: leading dimension smaller than the row length");
+    if (!ctx || (rows > 0 && k > 0 && (!X || !packed))) {
+        set_error("la_pack_bf16x3: NULL argument");
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t need = packed_x3_bytes(rows, k);
+    if (packed_bytes < need) {
+        set_error("la_pack_bf16x3: buffer %zu bytes, need %zu", packed_bytes, need);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    if (need == 0)
+        return LA_OK;
+    if (overlaps(packed, need, X, extent_bytes(kc ? rows : k, kc ? k : rows, ld))) {
+        set_error("la_pack_bf16x3: output overlaps X");
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_pack_bf16x3: hipSetDevice");
+    LA_HIP(launch_pack_x3(X, ld, kc ? 1 : 0, rows, k, packed, (hipStream_t)hip_stream),
+           "la_pack_bf16x3: launch");
+    return LA_OK;
+}
+
+la_status la_gemm_packed(la_context *ctx, int64_t m, int64_t n, int64_t k, float alpha,
+                         const void *Ap, const void *Bp, float beta, float *C, int64_t ldc,
+                         void *hip_stream)
+{
+    g_err[0] = 0;
+    if (m < 0 || n < 0 || k < 0 || ldc < std::max<int64_t>(n, 1)) {
+        set_error("la_gemm_packed: bad shape");
         return LA_ERR_SHAPE;
     }
     if (!ctx) {
-        set_error("la_gemm: ctx is NULL");
+        set_error("la_gemm_packed: ctx is NULL");
         return LA_ERR_INVALID_ARG;
     }
     if (m == 0 || n == 0)
         return LA_OK;
-    if (!C || (k > 0 && (!A || !B))) {
-        set_error("la_gemm: NULL matrix pointer");
+    if (!C || (k > 0 && (!Ap || !Bp))) {
+        set_error("la_gemm_packed: NULL argument");
         return LA_ERR_INVALID_ARG;
     }
     const size_t cb = extent_bytes(m, n, ldc);
-    if (k > 0 && (overlaps(C, cb, A, extent_bytes(a_rows, a_cols, lda)) ||
-                  overlaps(C, cb, B, extent_bytes(b_rows, b_cols, ldb)))) {
-        set_error("la_gemm: C overlaps A or B");
+    if (k > 0 && (overlaps(C, cb, Ap, packed_x3_bytes(m, k)) ||
+                  overlaps(C, cb, Bp, packed_x3_bytes(n, k)))) {
+        set_error("la_gemm_packed: C overlaps a packed operand");
         return LA_ERR_INVALID_ARG;
     }
-    LA_HIP(hipSetDevice(ctx->device), "la_gemm: hipSetDevice");
-    const int p = resolve_prec(prec, PREC_BF16X3);
+    LA_HIP(hipSetDevice(ctx->device), "la_gemm_packed: hipSetDevice");
     GemmDesc d;
     memset(&d, 0, sizeof d);
-    d.A = A;
-    d.lda = lda;
-    d.a_kcontig = trans_a ? 0 : 1;
-    d.B = B;
-    d.ldb = ldb;
-    d.b_kcontig = trans_b ? 1 : 0;
+    d.A = (const float *)Ap;
+    d.B = (const float *)Bp;
     d.C = C;
     d.ldc = ldc;
     d.M = m;
@@ -567,8 +672,66 @@ la_status la_gemm(la_context *ctx, int trans_a, int trans_b, int64_t m, int64_t 
         d.lde = ldc;
         d.beta = beta;
     }
-    gemm_finalize(d, p);
-    LA_HIP(launch_gemm(p, d, (hipStream_t)hip_stream), "la_gemm: launch");
+    d.tiles_m = (int)((m + 255) / 256);
+    d.tiles_n = (int)((n + 255) / 256);
+    d.num_tiles = d.tiles_m * d.tiles_n;
+    LA_HIP(launch_gemm_packed_x3(d, (hipStream_t)hip_stream), "la_gemm_packed: launch");
+    return LA_OK;
+}
+
+size_t la_gemm_workspace_size(int64_t m, int64_t n, int64_t k)
+{
+    if (m < 0 || n < 0 || k < 0)
+        return 0;
+    return align256(packed_x3_bytes(m, k)) + align256(packed_x3_bytes(n, k));
+}
+
+la_status la_gemm_ws(la_context *ctx, int trans_a, int trans_b, int64_t m, int64_t n, int64_t k,
+                     float alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                     float beta, float *C, int64_t ldc, la_precision prec, void *workspace,
+                     size_t ws_bytes, void *hip_stream)
+{
+    g_err[0] = 0;
+    GemmDesc d;
+    int p = 0;
+    bool empty = false;
+    la_status st = gemm_prepare("la_gemm_ws", ctx, trans_a, trans_b, m, n, k, alpha, A, lda, B,
+                                ldb, beta, C, ldc, prec, &d, &p, &empty);
+    if (st != LA_OK || empty)
+        return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    // packed path: 3xBF16 on 256 x 256 tiles with enough K to repay the pack pass
+    if (p != PREC_BF16X3 || d.small || k < 256) {
+        LA_HIP(launch_gemm(p, d, s), "la_gemm_ws: launch");
+        return LA_OK;
+    }
+    const size_t pa = align256(packed_x3_bytes(m, k)), need = pa + align256(packed_x3_bytes(n, k));
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0) {
+        set_error("la_gemm_ws: workspace must be non-NULL and 256-byte aligned");
+        return LA_ERR_INVALID_ARG;
+    }
+    if (ws_bytes < need) {
+        set_error("la_gemm_ws: workspace %zu bytes, need %zu", ws_bytes, need);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    const int64_t a_cols = trans_a ? m : k, a_rows = trans_a ? k : m;
+    const int64_t b_cols = trans_b ? k : n, b_rows = trans_b ? n : k;
+    if (overlaps(workspace, need, A, extent_bytes(a_rows, a_cols, lda)) ||
+        overlaps(workspace, need, B, extent_bytes(b_rows, b_cols, ldb)) ||
+        overlaps(workspace, need, C, extent_bytes(m, n, ldc))) {
+        set_error("la_gemm_ws: workspace overlaps A, B or C");
+        return LA_ERR_INVALID_ARG;
+    }
+    char *wa = (char *)workspace, *wb = wa + pa;
+    // op(A) rows are the output rows; op(B)^T rows are the output columns
+    LA_HIP(launch_pack_x3(A, lda, trans_a ? 0 : 1, m, k, wa, s), "la_gemm_ws: pack A");
+    LA_HIP(launch_pack_x3(B, ldb, trans_b ? 1 : 0, n, k, wb, s), "la_gemm_ws: pack B");
+    d.A = (const float *)wa;
+    d.B = (const float *)wb;
+    d.tiles_m = (int)((m + 255) / 256);
+    d.tiles_n = (int)((n + 255) / 256);
+    d.num_tiles = d.tiles_m * d.tiles_n;
+    LA_HIP(launch_gemm_packed_x3(d, s), "la_gemm_ws: launch");
     return LA_OK;
 }
 

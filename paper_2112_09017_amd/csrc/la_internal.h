@@ -67,6 +67,17 @@ hipError_t launch_gemm_grouped(int prec, int a_kcontig, int b_kcontig, int small
                                const GroupItem *items_dev, int num_items,
                                int grid_size, hipStream_t s);
 
+// Packed 3xBF16 operands (gemm_x3.hip): op(X) (rows x k; kc: k contiguous,
+// X[r * ld + k], else X[k * ld + r]) split into bf16 hi/lo terms and laid out
+// in the GEMM's LDS fragment order, zero-padded to 256 rows and 16 k.
+size_t packed_x3_bytes(int64_t rows, int64_t k);
+hipError_t launch_pack_x3(const float *X, int64_t ld, int kc, int64_t rows, int64_t k, void *out,
+                          hipStream_t s);
+// GEMM on packed operands: d.A and d.B point at packed op(A) (M x K) and
+// packed op(B)^T (N x K); 256 x 256 tiles (d.small must be 0).  Computes the
+// same products in the same order as the 3xBF16 kernel of launch_gemm.
+hipError_t launch_gemm_packed_x3(const GemmDesc &d, hipStream_t s);
+
 // Auxiliary kernels (aux_kernels.hip).
 // Sum of squares of an m x n strided matrix into nparts FP64 partials.
 int sumsq_num_partials();

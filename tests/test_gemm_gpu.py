@@ -178,3 +178,65 @@ def test_precision_ordering(la):
     print(e)
     assert e["BF16X6"] < e["BF16X3"] and e["FP32"] < e["BF16X3"]
     assert max(e.values()) <= TOL
+
+
+# ---------------------------------------------------------------- la_gemm_ws (packed operands)
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False), (True, True)])
+def test_gemm_ws_packed_bitwise_equals_gemm(la, ta, tb):
+    """Large enough for 256 x 256 tiles (>= 128 of them) with ragged M, N, K:
+    the packed-operand path must give la_gemm's result bit for bit (same
+    split, same products in the same order; zero padding adds exact zeros)."""
+    m, n, k = 3000, 2900, 1000
+    A = la_inputs.gaussian((k, m) if ta else (m, k), 301)
+    B = la_inputs.gaussian((n, k) if tb else (k, n), 302)
+    Ad = torch.from_numpy(A).to("cuda")
+    Bd = torch.from_numpy(B).to("cuda")
+    Aop = Ad.T if ta else Ad
+    Bop = Bd.T if tb else Bd
+    C0 = torch.from_numpy(la_inputs.gaussian((m, n), 303)).to("cuda")
+    C1 = C0.clone()
+    la.gemm(Aop, Bop, C0, alpha=0.75, beta=-0.5, prec=la.Precision.BF16X3)
+    la.gemm_ws(Aop, Bop, C1, alpha=0.75, beta=-0.5, prec=la.Precision.BF16X3)
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1)
+
+
+def test_gemm_ws_fallback_and_errors(la):
+    from paper_2112_09017_amd import LAError, Status
+    # small problem and other precisions: the la_gemm path, workspace untouched
+    A = torch.from_numpy(la_inputs.gaussian((300, 200), 304)).to("cuda")
+    B = torch.from_numpy(la_inputs.gaussian((200, 260), 305)).to("cuda")
+    for prec in (la.Precision.BF16X3, la.Precision.FP32, la.Precision.BF16X6):
+        C0 = la.gemm(A, B, prec=prec)
+        C1 = la.gemm_ws(A, B, prec=prec, workspace=torch.empty(0, dtype=torch.uint8,
+                                                                device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(C0, C1)
+    A = torch.from_numpy(la_inputs.gaussian((3000, 512), 306)).to("cuda")
+    B = torch.from_numpy(la_inputs.gaussian((512, 3000), 307)).to("cuda")
+    with pytest.raises(LAError) as e:
+        la.gemm_ws(A, B, workspace=torch.empty(4096, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == Status.OUT_OF_MEMORY
+
+
+def test_pack_then_gemm_packed_bitwise(la):
+    """la_pack_bf16x3 + la_gemm_packed (operands packed once, reused) equal
+    la_gemm at BF16X3 bit for bit, for a k-contiguous op(A) and a
+    row-contiguous op(B)^T, with ragged sizes and reuse of the same pack."""
+    m, n, k = 600, 520, 700
+    A = torch.from_numpy(la_inputs.gaussian((m, k), 310)).to("cuda")
+    B = torch.from_numpy(la_inputs.gaussian((k, n), 311)).to("cuda")
+    Ap = la.pack_bf16x3(A)            # op(A) = A, k contiguous
+    Bp = la.pack_bf16x3(B.T)          # op(B)^T = B^T, a transposed view
+    C0 = la.gemm(A, B, prec=la.Precision.BF16X3)
+    C1 = la.gemm_packed(Ap, Bp, m, n, k)
+    C2 = la.gemm_packed(Ap, Bp, m, n, k)
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1) and torch.equal(C1, C2)
+    # Gram from one pack: A^T A with op(A) = A^T and op(B)^T = A^T
+    At = la.pack_bf16x3(A.T)
+    G0 = la.gemm(A.T, A, prec=la.Precision.BF16X3)
+    G1 = la.gemm_packed(At, At, k, k, m)
+    torch.cuda.synchronize()
+    assert torch.equal(G0, G1)
