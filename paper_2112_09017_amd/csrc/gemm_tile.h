@@ -1002,29 +1002,52 @@ constexpr int kPackSlabK = 128;   // k covered by one workgroup of the pack kern
 template <bool KC>
 __global__ void __launch_bounds__(256) pack_x3_kernel(const float *__restrict__ X, int64_t ld,
                                                       int64_t R, int64_t K, int64_t kbt,
-                                                      int64_t rbt, char *__restrict__ out)
+                                                      int64_t rbt, int vec,
+                                                      char *__restrict__ out)
 {
     __shared__ float tile[32][kPackSlabK + 1];
     const int t = threadIdx.x;
     for (int64_t rb = blockIdx.y; rb < rbt; rb += gridDim.y) {
         const int64_t r0 = rb * 32, k0 = (int64_t)blockIdx.x * kPackSlabK;
-        // stage 32 rows x 128 k through LDS (consecutive threads read
-        // consecutive addresses in either storage order); zero outside R x K
-#pragma unroll 4
-        for (int i = t; i < 32 * kPackSlabK; i += 256) {
-            int r, k;
+        // stage 32 rows x 128 k through LDS, 4 consecutive elements of the
+        // contiguous direction per thread and load (consecutive threads read
+        // consecutive 16 bytes); zero outside R x K.  vec: the operand allows
+        // 16-byte loads (aligned base, ld a multiple of 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = t + 256 * u;            // 1024 groups of 4 elements
+            int r, k;                             // first element of the group
             if (KC) {
-                r = i / kPackSlabK;
-                k = i % kPackSlabK;
+                r = i / (kPackSlabK / 4);
+                k = (i % (kPackSlabK / 4)) * 4;
             } else {
-                k = i / 32;
-                r = i % 32;
+                k = i / 8;
+                r = (i % 8) * 4;
             }
             const int64_t gr = r0 + r, gk = k0 + k;
-            float v = 0.0f;
-            if (gr < R && gk < K)
-                v = KC ? X[gr * ld + gk] : X[gk * ld + gr];
-            tile[r][k] = v;
+            float v[4];
+            const bool full = KC ? (gr < R && gk + 3 < K) : (gk < K && gr + 3 < R);
+            if (vec && full) {
+                const f32x4 q = *reinterpret_cast<const f32x4 *>(KC ? X + gr * ld + gk
+                                                                    : X + gk * ld + gr);
+                v[0] = q[0];
+                v[1] = q[1];
+                v[2] = q[2];
+                v[3] = q[3];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t er = KC ? gr : gr + e, ek = KC ? gk + e : gk;
+                    v[e] = (er < R && ek < K) ? (KC ? X[er * ld + ek] : X[ek * ld + er]) : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (KC)
+                    tile[r][k + e] = v[e];
+                else
+                    tile[r + e][k] = v[e];
+            }
         }
         __syncthreads();
         // 8 k blocks x 64 lane entries per term; two entries per thread
@@ -1326,12 +1349,13 @@ inline hipError_t launch_pack_x3(const float *X, int64_t ld, int kc, int64_t R, 
     if (gx > 0x7fffffff)
         return hipErrorInvalidValue;
     const unsigned gy = (unsigned)(rbt < 65535 ? rbt : 65535);
+    const int vec = ((uintptr_t)X % 16 == 0 && ld % 4 == 0) ? 1 : 0;
     if (kc)
         hipLaunchKernelGGL((pack_x3_kernel<true>), dim3((unsigned)gx, gy), dim3(256), 0, s, X, ld,
-                           R, K, kbt, rbt, out);
+                           R, K, kbt, rbt, vec, out);
     else
         hipLaunchKernelGGL((pack_x3_kernel<false>), dim3((unsigned)gx, gy), dim3(256), 0, s, X, ld,
-                           R, K, kbt, rbt, out);
+                           R, K, kbt, rbt, vec, out);
     return hipGetLastError();
 }
 

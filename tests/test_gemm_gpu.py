@@ -240,3 +240,17 @@ def test_pack_then_gemm_packed_bitwise(la):
     G1 = la.gemm_packed(At, At, k, k, m)
     torch.cuda.synchronize()
     assert torch.equal(G0, G1)
+
+
+def test_pack_unaligned_operands_bitwise(la):
+    """Operands that are views at an odd offset (no 16-byte loads) pack through
+    the element-wise path and still give la_gemm's result bit for bit."""
+    m, n, k = 2900, 2800, 513
+    Abig = torch.from_numpy(la_inputs.gaussian((m, k + 3), 312)).to("cuda")
+    Bbig = torch.from_numpy(la_inputs.gaussian((k, n + 1), 313)).to("cuda")
+    A = Abig[:, 1:k + 1]          # ld = k + 3, base misaligned by 4 bytes
+    B = Bbig[:, 1:]               # ld = n + 1
+    C0 = la.gemm(A, B, prec=la.Precision.BF16X3)
+    C1 = la.gemm_ws(A, B, prec=la.Precision.BF16X3)
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1)
