@@ -990,14 +990,29 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
 
 // Packed layout of an R x K operand op(X) (R = output rows for A, output
 // columns for B), written by pack_x3_kernel and read by gemm_packed_kernel:
-// 1 KiB chunks, chunk (rb, kb, t) at byte ((rb * KB + kb) * 2 + t) * 1024,
-// rb = block of 32 rows, kb = block of 16 k, t = term (0 hi, 1 lo).  Inside
+// 1 KiB chunks, chunk (rb, kb, t) at byte kb * packed_kstride(RB) +
+// (rb * 2 + t) * 1024, rb = block of 32 rows (RB of them), kb = block of 16
+// k, t = term (0 hi, 1 lo).  k-block-major: one stage of one tile is 16
+// contiguous KiB, and all tiles at the same k step read one contiguous
+// region (a row-block-major order put the chunks in flight a power of two
+// apart, which defeated the L2).  Inside
 // a chunk, the 16 bytes of lane l hold the 8 bf16 of row 32 rb + (l & 31),
 // k = 16 kb + 8 (l >> 5) .. + 7: exactly one fragment block of the LDS image
 // (entry_off with KF = 1).  Rows are padded with zeros to a multiple of 256,
 // k to a multiple of 16, so the GEMM needs no bounds checks.
 constexpr int kPackRows = 256;
 constexpr int kPackSlabK = 128;   // k covered by one workgroup of the pack kernel
+// Bytes from one k block to the next in a packed operand with rbt row
+// blocks: the 2 rbt KiB of chunks plus 17 KiB of padding.  Without it the
+// stride is a power of two for power-of-two sizes, consecutive k blocks land
+// in the same L2 sets, and the L2 misses doubled (measured at
+// 16384 x 32768 x 16384: 151 GiB fetched per launch unpadded, 72 GiB with
+// 17 KiB, which fetched the least among the paddings tried).
+constexpr int kPackPadKiB = 17;
+__host__ __device__ inline int64_t packed_kstride(int64_t rbt)
+{
+    return (2 * rbt + kPackPadKiB) << 10;
+}
 
 template <bool KC>
 __global__ void __launch_bounds__(256) pack_x3_kernel(const float *__restrict__ X, int64_t ld,
@@ -1063,7 +1078,7 @@ __global__ void __launch_bounds__(256) pack_x3_kernel(const float *__restrict__ 
                 v[j] = tile[r][kk + j];
             u32x4 parts[2];
             Split<PREC_BF16X3>::run(v, parts);
-            char *chunk = out + (((rb * kbt + kb) * 2) << 10);
+            char *chunk = out + kb * packed_kstride(rbt) + ((rb * 2) << 10);
             *reinterpret_cast<u32x4 *>(chunk + lane * 16) = parts[0];
             *reinterpret_cast<u32x4 *>(chunk + 1024 + lane * 16) = parts[1];
         }
@@ -1100,25 +1115,25 @@ __device__ __forceinline__ uint32_t lds_offset(const void *p)
 // A (2 terms x 8 row blocks) and 16 of B.  Wave w moves operand (w >= 2 ? B
 // : A), term (w & 1), row blocks 0..7: eight 1 KiB chunks, each one
 // global_load_lds_dwordx4.  stage_lds: LDS byte offset of the stage buffer.
+// rbta / rbtb: row blocks of the packed A / B (the RB of the layout).
 template <int P>
-__device__ __forceinline__ void packed_issue(const char *pa, const char *pb, int64_t kbt,
-                                             int64_t rba, int64_t rbb, int64_t kb,
+__device__ __forceinline__ void packed_issue(const char *pa, const char *pb, int64_t rbta,
+                                             int64_t rbtb, int64_t rba, int64_t rbb, int64_t kb,
                                              uint32_t stage_lds, int w, int lane)
 {
     using G = Geo<P>;
     const bool isb = w >= 2;
     const char *base = isb ? pb : pa;
-    const int64_t rb0 = isb ? rbb : rba;
+    const int64_t rb0 = isb ? rbb : rba, rbt = isb ? rbtb : rbta;
     const uint32_t dst0 = stage_lds + (isb ? G::a_bytes : 0);
     const int tt = w & 1;
-    const uint64_t wb = (uint64_t)(base + (((rb0 * kbt + kb) * 2 + tt) << 10));
+    const uint64_t wb = (uint64_t)(base + kb * packed_kstride(rbt) + ((rb0 * 2 + tt) << 10));
     const char *wbase = (const char *)(
         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(wb >> 32)) << 32) |
         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wb));
-    const int64_t rb_stride = kbt << 11;   // bytes between consecutive row blocks
 #pragma unroll
-    for (int frow = 0; frow < 8; ++frow)
-        dma16(wbase + frow * rb_stride, lane * 16, dst0 + ((tt * 8 + frow) << 10));
+    for (int frow = 0; frow < 8; ++frow)   // consecutive row blocks are 2 KiB apart
+        dma16(wbase + (frow << 11), lane * 16, dst0 + ((tt * 8 + frow) << 10));
 }
 
 // Fragments of one packed stage for this wave, in two halves: the operands
@@ -1181,8 +1196,9 @@ template <int P>
 __device__ __forceinline__ void packed_stage(int ss, int nst, f32x16 (&acc)[Geo<P>::FM][Geo<P>::FN],
                                              bf16x8 (&alo)[Geo<P>::FM], bf16x8 (&bhi)[Geo<P>::FN],
                                              const char *smem, uint32_t smem_lds, const char *pa,
-                                             const char *pb, int64_t kbt, int64_t rba, int64_t rbb,
-                                             int w, int wm, int wn, int lane)
+                                             const char *pb, int64_t rbta, int64_t rbtb,
+                                             int64_t rba, int64_t rbb, int w, int wm, int wn,
+                                             int lane)
 {
     using C = Cfg<P>;
     using G = Geo<P>;
@@ -1208,8 +1224,8 @@ __device__ __forceinline__ void packed_stage(int ss, int nst, f32x16 (&acc)[Geo<
         asm volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
         if (ss + NS < nst)
-            packed_issue<P>(pa, pb, kbt, rba, rbb, ss + NS, smem_lds + (ss & (NS - 1)) * G::stage_bytes,
-                            w, lane);
+            packed_issue<P>(pa, pb, rbta, rbtb, rba, rbb, ss + NS,
+                            smem_lds + (ss & (NS - 1)) * G::stage_bytes, w, lane);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
             alo[i] = *reinterpret_cast<const bf16x8 *>(nst_ + frag_off<C::BM, 1, 16>(1, wm * FM + i, 0, lane));
@@ -1252,6 +1268,7 @@ __global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
     const char *pb = reinterpret_cast<const char *>(d.B);
     const int64_t kbt = (d.K + 15) / 16;
     const int64_t rba = (int64_t)tm * 8, rbb = (int64_t)tn * 8;
+    const int64_t rbta = (int64_t)d.tiles_m * 8, rbtb = (int64_t)d.tiles_n * 8;
     const int nst = (int)kbt;
     const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_offset(smem));
     // first-product fragments of the current stage
@@ -1260,15 +1277,16 @@ __global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (s < nst)
-                packed_issue<P>(pa, pb, kbt, rba, rbb, s, smem_lds + s * G::stage_bytes, w, lane);
+                packed_issue<P>(pa, pb, rbta, rbtb, rba, rbb, s, smem_lds + s * G::stage_bytes, w,
+                                lane);
         packed_wait(min(nst - 1, NS - 1));
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         packed_read_first<P>(smem, alo, bhi, wm, wn, lane);
     }
     for (int s = 0; s < nst; ++s)
-        packed_stage<P>(s, nst, acc, alo, bhi, smem, smem_lds, pa, pb, kbt, rba, rbb, w, wm, wn,
-                        lane);
+        packed_stage<P>(s, nst, acc, alo, bhi, smem, smem_lds, pa, pb, rbta, rbtb, rba, rbb, w, wm,
+                        wn, lane);
     epilogue<P>(d, acc, tm, tn, wm, wn, lane, red);
 }
 
@@ -1335,7 +1353,7 @@ inline size_t packed_bytes(int64_t R, int64_t K)
 {
     const int64_t rbt = (R + kPackRows - 1) / kPackRows * (kPackRows / 32);
     const int64_t kbt = (K + 15) / 16;
-    return (size_t)rbt * (size_t)kbt * 2048;
+    return rbt == 0 ? 0 : (size_t)kbt * (size_t)packed_kstride(rbt);
 }
 
 inline hipError_t launch_pack_x3(const float *X, int64_t ld, int kc, int64_t R, int64_t K,
