@@ -13,6 +13,11 @@ GPU library computes, written from the paper (arXiv 2112.09017):
 * ``matfunc_odd``  -- odd polynomial of the singular values (eq. OddPoly);
 * ``matfunc_cheb`` -- Chebyshev polynomial of the eigenvalues
                    (eq. EigenvaluePolynomial);
+* ``householder_qr`` -- reduced QR by Householder reflections (the local
+                   factorisation of section III.B);
+* ``tsqr``      -- Algorithm tsqr (row blocks, pairwise reduction of R);
+* ``yamamoto``  -- the W, Y factors of eq. (Yamamoto);
+* ``caqr``      -- Algorithm caqr (right-looking panel QR);
 * scalar maps   -- eqs. (NS_scalar), (a_def), (RogueScalar) and the
                    preconditioning step count of Algorithm NS_Polar.
 
@@ -108,6 +113,14 @@ def _bind(path: str):
     lib.orc_matfunc_cheb.argtypes = [i64, dp, i64, ctypes.c_double, ctypes.c_double, dp,
                                      ctypes.c_int, dp, i64]
     lib.orc_matfunc_cheb.restype = ctypes.c_int
+    lib.orc_householder_qr.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
+    lib.orc_householder_qr.restype = ctypes.c_int
+    lib.orc_tsqr.argtypes = [i64, i64, dp, i64, i64, dp, i64, dp, i64]
+    lib.orc_tsqr.restype = ctypes.c_int
+    lib.orc_yamamoto.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64]
+    lib.orc_yamamoto.restype = ctypes.c_int
+    lib.orc_caqr.argtypes = [i64, i64, dp, i64, i64, i64, dp, i64, dp, i64]
+    lib.orc_caqr.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     return lib
@@ -256,6 +269,58 @@ class Oracle:
             raise ValueError("orc_matfunc_cheb: bad arguments or allocation failure")
         return F
 
+    def householder_qr(self, A):
+        """Reduced QR (Q m x n, R n x n upper triangular) of an m x n A, m >= n,
+        by Householder reflections with R_jj of the sign opposite to A_jj."""
+        A = _f64(A)
+        m, n = A.shape
+        Q = np.zeros((m, n))
+        R = np.zeros((n, n))
+        if self._lib.orc_householder_qr(m, n, _ptr(A), n, _ptr(Q), n, _ptr(R), n) != 0:
+            raise ValueError("orc_householder_qr: bad arguments or allocation failure")
+        return Q, R
+
+    def tsqr(self, A, block_rows: int):
+        """Algorithm tsqr with row blocks of ``block_rows`` (>= n) rows; the last
+        block takes the remainder.  Returns (Q, R)."""
+        A = _f64(A)
+        m, n = A.shape
+        Q = np.zeros((m, n))
+        R = np.zeros((n, n))
+        if self._lib.orc_tsqr(m, n, _ptr(A), n, block_rows, _ptr(Q), n, _ptr(R), n) != 0:
+            raise ValueError("orc_tsqr: bad arguments or allocation failure")
+        return Q, R
+
+    def yamamoto(self, Q):
+        """W = Q - [I; 0] and Y = W (I - Q_1)^-1 (eq. Yamamoto with T^-1 read as
+        (I - Q_1)^T), so that I - W Y^T is the full orthogonal factor whose
+        first n columns are Q."""
+        Q = _f64(Q)
+        m, n = Q.shape
+        W = np.zeros((m, n))
+        Y = np.zeros((m, n))
+        rc = self._lib.orc_yamamoto(m, n, _ptr(Q), n, _ptr(W), n, _ptr(Y), n)
+        if rc == -3:
+            raise np.linalg.LinAlgError("I - Q_1 is singular")
+        if rc != 0:
+            raise ValueError("orc_yamamoto: bad arguments or allocation failure")
+        return W, Y
+
+    def caqr(self, A, panel: int, block_rows: int, want_q: bool = True):
+        """Algorithm caqr: panels of ``panel`` columns (dividing n), each by tsqr
+        with row blocks of ``block_rows``.  Returns (Q or None, R)."""
+        A = _f64(A)
+        m, n = A.shape
+        Q = np.zeros((m, n)) if want_q else None
+        R = np.zeros((n, n))
+        rc = self._lib.orc_caqr(m, n, _ptr(A), n, panel, block_rows,
+                                _ptr(Q) if want_q else None, n, _ptr(R), n)
+        if rc == -3:
+            raise np.linalg.LinAlgError("I - Q_1 is singular in a panel")
+        if rc != 0:
+            raise ValueError("orc_caqr: bad arguments or allocation failure")
+        return Q, R
+
     def polar_2x2(self, A):
         """Closed-form polar factors (U, H) of a full-rank 2 x 2 matrix."""
         A = _f64(A).reshape(2, 2)
@@ -312,6 +377,22 @@ def matfunc_odd(*a, **k):
 
 def matfunc_cheb(*a, **k):
     return _load().matfunc_cheb(*a, **k)
+
+
+def householder_qr(*a, **k):
+    return _load().householder_qr(*a, **k)
+
+
+def tsqr(*a, **k):
+    return _load().tsqr(*a, **k)
+
+
+def yamamoto(*a, **k):
+    return _load().yamamoto(*a, **k)
+
+
+def caqr(*a, **k):
+    return _load().caqr(*a, **k)
 
 
 def num_threads():

@@ -486,3 +486,307 @@ int orc_matfunc_cheb(int64_t n, const double *A, int64_t lda, double lo,
     free(B); free(Tp); free(Tc); free(Tn);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* QR factorisation (section III.B): Householder QR as the local step,      */
+/* Algorithm tsqr, the Yamamoto WY form (eq. Yamamoto) and Algorithm caqr.  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Reduced QR of an m x n A (m >= n) by Householder reflections: for column
+ * j, x = A[j:, j], beta = -sign(x_0) ||x||, v = x - beta e_1 scaled so that
+ * v_0 = 1, tau = (beta - x_0) / beta, and A[j:, j:] <- (I - tau v v^T)
+ * A[j:, j:].  R (n x n, ldr) = the upper triangle; Q (m x n, ldq) =
+ * H_0 ... H_{n-1} [I_n; 0], formed by applying the reflections to [I; 0]
+ * in reverse order.  Either output may be NULL.  Returns 0 or -1.
+ */
+int orc_householder_qr(int64_t m, int64_t n, const double *A, int64_t lda,
+                       double *Q, int64_t ldq, double *R, int64_t ldr)
+{
+    if (m < n || n < 1 || lda < n)
+        return -1;
+    double *W = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *tau = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!W || !tau || !w) {
+        free(W); free(tau); free(w);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            W[i * n + j] = A[i * lda + j];
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t i = j; i < m; ++i)
+            s += W[i * n + j] * W[i * n + j];
+        const double nrm = sqrt(s);
+        const double x0 = W[j * n + j];
+        if (nrm == 0.0) {           /* zero column: no reflection */
+            tau[j] = 0.0;
+            continue;
+        }
+        const double beta = x0 >= 0.0 ? -nrm : nrm;
+        tau[j] = (beta - x0) / beta;
+        const double scale = 1.0 / (x0 - beta);
+        for (int64_t i = j + 1; i < m; ++i)
+            W[i * n + j] *= scale;          /* v below the diagonal, v_0 = 1 */
+        W[j * n + j] = beta;
+        /* A[j:, j+1:] <- (I - tau v v^T) A[j:, j+1:] */
+        for (int64_t c = j + 1; c < n; ++c) {
+            double d = W[j * n + c];
+            for (int64_t i = j + 1; i < m; ++i)
+                d += W[i * n + j] * W[i * n + c];
+            w[c] = tau[j] * d;
+        }
+        for (int64_t c = j + 1; c < n; ++c) {
+            W[j * n + c] -= w[c];
+            for (int64_t i = j + 1; i < m; ++i)
+                W[i * n + c] -= W[i * n + j] * w[c];
+        }
+    }
+    if (R)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                R[i * ldr + j] = j >= i ? W[i * n + j] : 0.0;
+    if (Q) {
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
+        for (int64_t j = n - 1; j >= 0; --j) {
+            if (tau[j] == 0.0)
+                continue;
+            /* Q[j:, :] <- (I - tau v v^T) Q[j:, :] */
+            for (int64_t c = 0; c < n; ++c) {
+                double d = Q[j * ldq + c];
+                for (int64_t i = j + 1; i < m; ++i)
+                    d += W[i * n + j] * Q[i * ldq + c];
+                w[c] = tau[j] * d;
+            }
+            for (int64_t c = 0; c < n; ++c) {
+                Q[j * ldq + c] -= w[c];
+                for (int64_t i = j + 1; i < m; ++i)
+                    Q[i * ldq + c] -= W[i * n + j] * w[c];
+            }
+        }
+    }
+    free(W); free(tau); free(w);
+    return 0;
+}
+
+/*
+ * Algorithm tsqr: A (m x n) is split into row blocks of mr rows (mr >= n;
+ * the last block takes the remainder and is merged into the one before it
+ * if it has fewer than n rows).  Each block is factored (Householder QR);
+ * then, while more than one R remains, neighbouring groups are paired, their
+ * R factors stacked and factored again, and each group's Q rows are
+ * multiplied by its half of the pair's Q factor (the optional step, here
+ * always taken).  Q (m x n, ldq) and R (n x n, ldr).  Returns 0 or -1.
+ */
+int orc_tsqr(int64_t m, int64_t n, const double *A, int64_t lda, int64_t mr,
+             double *Q, int64_t ldq, double *R, int64_t ldr)
+{
+    if (m < n || n < 1 || lda < n || mr < n || ldq < n || ldr < n)
+        return -1;
+    int64_t p = m / mr;   /* blocks of mr rows; the last one takes the remainder */
+    if (p < 1)
+        p = 1;
+    int64_t *r0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)(p + 1));
+    double *Rs = (double *)malloc(sizeof(double) * (size_t)(p * n * n));
+    double *S = (double *)malloc(sizeof(double) * (size_t)(2 * n * n));
+    double *Qp = (double *)malloc(sizeof(double) * (size_t)(2 * n * n));
+    double *T = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    if (!r0 || !Rs || !S || !Qp || !T) {
+        free(r0); free(Rs); free(S); free(Qp); free(T);
+        return -1;
+    }
+    for (int64_t i = 0; i < p; ++i)
+        r0[i] = i * mr;
+    r0[p] = m;
+    /* local factorisations */
+    for (int64_t i = 0; i < p; ++i) {
+        const int64_t rows = r0[i + 1] - r0[i];
+        if (orc_householder_qr(rows, n, A + r0[i] * lda, lda, Q + r0[i] * ldq, ldq,
+                               Rs + i * n * n, n) != 0) {
+            free(r0); free(Rs); free(S); free(Qp); free(T);
+            return -1;
+        }
+    }
+    /* binary reduction: groups of size g (in blocks), leader = first block */
+    for (int64_t g = 1; g < p; g *= 2) {
+        for (int64_t a = 0; a + g < p; a += 2 * g) {
+            const int64_t b = a + g;             /* leader of the right group */
+            const int64_t end = (b + g < p) ? b + g : p;
+            /* stack R_a over R_b and factor */
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t j = 0; j < n; ++j) {
+                    S[i * n + j] = Rs[a * n * n + i * n + j];
+                    S[(n + i) * n + j] = Rs[b * n * n + i * n + j];
+                }
+            if (orc_householder_qr(2 * n, n, S, n, Qp, n, Rs + a * n * n, n) != 0) {
+                free(r0); free(Rs); free(S); free(Qp); free(T);
+                return -1;
+            }
+            /* Q rows of the left group times the top half, right group times the bottom */
+            for (int half = 0; half < 2; ++half) {
+                const int64_t lo = r0[half ? b : a], hi = r0[half ? end : b];
+                const double *H = Qp + (half ? n * n : 0);
+                orc_gemm(0, 0, hi - lo, n, n, 1.0, Q + lo * ldq, ldq, H, n, 0.0, T, n);
+                for (int64_t i = lo; i < hi; ++i)
+                    for (int64_t j = 0; j < n; ++j)
+                        Q[i * ldq + j] = T[(i - lo) * n + j];
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            R[i * ldr + j] = Rs[i * n + j];
+    free(r0); free(Rs); free(S); free(Qp); free(T);
+    return 0;
+}
+
+/*
+ * eq. (Yamamoto): from the reduced Q (m x n) of a panel, W = Q - [I_n; 0],
+ * Q_1 = the first n rows of Q, and Y with Y^T = T W^T.  The full factor
+ * Q_f = I - W Y^T must reproduce Q in its first n columns (A_l = Q_f R_f),
+ * i.e. [I; 0] + W = [I; 0] - W T (Q_1 - I)^T, which fixes T^{-1} =
+ * (I - Q_1)^T: the equation read with T^{-1} as the transpose of I - Q_1.
+ * Then Y = W (I - Q_1)^{-1}: each row y of Y solves (I - Q_1)^T y^T = w^T,
+ * by Gaussian elimination with partial pivoting.  W, Y: m x n (ldw, ldy).
+ * Returns 0, -1 on bad arguments, -3 if I - Q_1 is singular.
+ */
+int orc_yamamoto(int64_t m, int64_t n, const double *Q, int64_t ldq, double *W,
+                 int64_t ldw, double *Y, int64_t ldy)
+{
+    if (m < n || n < 1 || ldq < n || ldw < n || ldy < n)
+        return -1;
+    double *M = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    int64_t *piv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    double *x = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!M || !piv || !x) {
+        free(M); free(piv); free(x);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            W[i * ldw + j] = Q[i * ldq + j] - ((i == j) ? 1.0 : 0.0);
+    /* M = (I - Q_1)^T, LU with partial pivoting: P M = L U (in place) */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            M[i * n + j] = ((i == j) ? 1.0 : 0.0) - Q[j * ldq + i];
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t pr = k;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(M[i * n + k]) > fabs(M[pr * n + k]))
+                pr = i;
+        piv[k] = pr;
+        if (M[pr * n + k] == 0.0) {
+            free(M); free(piv); free(x);
+            return -3;
+        }
+        if (pr != k)
+            for (int64_t j = 0; j < n; ++j) {
+                double t = M[k * n + j]; M[k * n + j] = M[pr * n + j]; M[pr * n + j] = t;
+            }
+        for (int64_t i = k + 1; i < n; ++i) {
+            M[i * n + k] /= M[k * n + k];
+            for (int64_t j = k + 1; j < n; ++j)
+                M[i * n + j] -= M[i * n + k] * M[k * n + j];
+        }
+    }
+    /* each row: (I - Q_1)^T y^T = w^T */
+    for (int64_t r = 0; r < m; ++r) {
+        for (int64_t j = 0; j < n; ++j)
+            x[j] = W[r * ldw + j];
+        for (int64_t k = 0; k < n; ++k)
+            if (piv[k] != k) {
+                double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t;
+            }
+        for (int64_t i = 1; i < n; ++i)
+            for (int64_t j = 0; j < i; ++j)
+                x[i] -= M[i * n + j] * x[j];
+        for (int64_t i = n - 1; i >= 0; --i) {
+            for (int64_t j = i + 1; j < n; ++j)
+                x[i] -= M[i * n + j] * x[j];
+            x[i] /= M[i * n + i];
+        }
+        for (int64_t j = 0; j < n; ++j)
+            Y[r * ldy + j] = x[j];
+    }
+    free(M); free(piv); free(x);
+    return 0;
+}
+
+/*
+ * Algorithm caqr (right-looking): for each panel of b columns starting at
+ * column c = j b, A_l = A[c:, c:c+b] is factored by tsqr (row blocks of mr),
+ * A_l is replaced by [R_r; 0], W and Y are formed (eq. Yamamoto) and the
+ * columns to the right are replaced by Q_f^T A_r = A_r - Y (W^T A_r).  R
+ * (n x n, ldr) is the upper triangle of the result; Q (m x n, ldq, may be
+ * NULL) is the reduced Q factor, Q_f(0) Q_f(1) ... [I_n; 0] with each Q_f
+ * acting on rows c:.  n must be a multiple of b.  Returns 0, -1, or -3 (a
+ * singular I - Q_1).
+ */
+int orc_caqr(int64_t m, int64_t n, const double *A, int64_t lda, int64_t b, int64_t mr,
+             double *Q, int64_t ldq, double *R, int64_t ldr)
+{
+    if (m < n || n < 1 || b < 1 || n % b != 0 || mr < b || lda < n || ldr < n ||
+        (Q && ldq < n))
+        return -1;
+    const int64_t np = n / b;
+    double *X = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *Qr = (double *)malloc(sizeof(double) * (size_t)(m * b));
+    double *Rr = (double *)malloc(sizeof(double) * (size_t)(b * b));
+    double *Ws = (double *)malloc(sizeof(double) * (size_t)(m * n));   /* W of every panel */
+    double *Ys = (double *)malloc(sizeof(double) * (size_t)(m * n));
+    double *Z = (double *)malloc(sizeof(double) * (size_t)(b * n));
+    double *Ac = (double *)malloc(sizeof(double) * (size_t)(m * b));
+    if (!X || !Qr || !Rr || !Ws || !Ys || !Z || !Ac) {
+        free(X); free(Qr); free(Rr); free(Ws); free(Ys); free(Z); free(Ac);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            X[i * n + j] = A[i * lda + j];
+    int rc = 0;
+    for (int64_t jp = 0; jp < np && rc == 0; ++jp) {
+        const int64_t c = jp * b, ml = m - c, nr = n - c - b;
+        double *W = Ws + c * n + c;   /* W of panel jp: rows c.., columns c..c+b (ld n) */
+        double *Y = Ys + c * n + c;
+        for (int64_t i = 0; i < ml; ++i)
+            for (int64_t j = 0; j < b; ++j)
+                Ac[i * b + j] = X[(c + i) * n + c + j];
+        rc = orc_tsqr(ml, b, Ac, b, mr < ml ? mr : ml, Qr, b, Rr, b);
+        if (rc == 0)
+            rc = orc_yamamoto(ml, b, Qr, b, W, n, Y, n);
+        if (rc != 0)
+            break;
+        for (int64_t i = 0; i < ml; ++i)
+            for (int64_t j = 0; j < b; ++j)
+                X[(c + i) * n + c + j] = i < b ? Rr[i * b + j] : 0.0;
+        if (nr > 0) {
+            /* Z = W^T A_r (b x nr);  A_r <- A_r - Y Z */
+            orc_gemm(1, 0, b, nr, ml, 1.0, W, n, X + c * n + c + b, n, 0.0, Z, nr);
+            orc_gemm(0, 0, ml, nr, b, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);
+        }
+    }
+    if (rc == 0) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                R[i * ldr + j] = j >= i ? X[i * n + j] : 0.0;
+        if (Q) {
+            /* Q = Q_f(0) ... Q_f(np-1) [I_n; 0], applied from the last panel back */
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t j = 0; j < n; ++j)
+                    Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
+            for (int64_t jp = np - 1; jp >= 0; --jp) {
+                const int64_t c = jp * b, ml = m - c;
+                const double *W = Ws + c * n + c, *Y = Ys + c * n + c;
+                /* Q[c:, :] <- Q[c:, :] - W (Y^T Q[c:, :]) */
+                orc_gemm(1, 0, b, n, ml, 1.0, Y, n, Q + c * ldq, ldq, 0.0, Z, n);
+                orc_gemm(0, 0, ml, n, b, -1.0, W, n, Z, n, 1.0, Q + c * ldq, ldq);
+            }
+        }
+    }
+    free(X); free(Qr); free(Rr); free(Ws); free(Ys); free(Z); free(Ac);
+    return rc;
+}

@@ -478,6 +478,96 @@ def pin_matfunc_cheb_exponential(orc):
     assert np.max(np.abs(F - scipy.linalg.expm(A))) < 1e-12
 
 
+# --------------------------------------------------------------------------- QR (section III.B)
+
+def _pos_diag(Q, R):
+    """Normalise a QR pair to a positive diagonal of R (QR is unique up to
+    the signs of R's rows for a full-rank A)."""
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :], R * d[:, None]
+
+
+def _check_qr(A, Q, R, tol=1e-12):
+    m, n = A.shape
+    assert Q.shape == (m, n) and R.shape == (n, n)
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    assert np.linalg.norm(Q @ R - A) <= tol * np.linalg.norm(A)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= tol * math.sqrt(n)
+    Qn, Rn = _pos_diag(*np.linalg.qr(A))     # LAPACK's Householder QR
+    Qp, Rp = _pos_diag(Q, R)
+    assert np.max(np.abs(Rp - Rn)) <= tol * 100 * np.max(np.abs(Rn))
+    assert np.max(np.abs(Qp - Qn)) <= tol * 100
+
+
+def pin_qr_2x2_golden(orc):
+    g = _golden("qr_2x2.json")
+    Q, R = orc.householder_qr(np.array(g["A"]))
+    assert np.max(np.abs(Q - np.array(g["Q"]))) < 1e-15
+    assert np.max(np.abs(R - np.array(g["R"]))) < 1e-14
+    q, r = orc.householder_qr(np.array([[3.0], [4.0]]))
+    assert abs(r[0, 0] + 5.0) < 1e-15 and np.max(np.abs(q[:, 0] + np.array([0.6, 0.8]))) < 1e-15
+
+
+def pin_qr_householder_vs_numpy(orc):
+    for shape, seed in (((60, 20), 700), ((33, 33), 701), ((257, 64), 702)):
+        A = la_inputs.gaussian(shape, seed).astype(np.float64)
+        _check_qr(A, *orc.householder_qr(A))
+    # an upper-triangular input with a positive diagonal is its own R up to signs
+    R0 = np.triu(la_inputs.gaussian((16, 16), 703).astype(np.float64)) + 4 * np.eye(16)
+    Q, R = _pos_diag(*orc.householder_qr(R0))
+    assert np.max(np.abs(R - R0)) < 1e-13 and np.max(np.abs(Q - np.eye(16))) < 1e-14
+
+
+def pin_qr_tsqr(orc):
+    """Algorithm tsqr gives the same factorisation as one Householder QR (up to
+    the row signs of R) for every block height, including a ragged remainder
+    and trees of 2, 3 and 5 levels; one block is the local QR itself."""
+    A = la_inputs.gaussian((300, 24), 704).astype(np.float64)
+    Q1, R1 = orc.householder_qr(A)
+    for mr in (24, 37, 50, 64, 100, 150, 300):
+        Q, R = orc.tsqr(A, mr)
+        _check_qr(A, Q, R)
+    Q, R = orc.tsqr(A, 300)
+    assert np.array_equal(Q, Q1) and np.array_equal(R, R1)
+
+
+def pin_qr_yamamoto(orc):
+    """eq. (Yamamoto): I - W Y^T is orthogonal and its first n columns are Q;
+    for one column it is the reflection taking e_1 to q."""
+    A = la_inputs.gaussian((90, 12), 705).astype(np.float64)
+    Q, _ = orc.tsqr(A, 30)
+    W, Y = orc.yamamoto(Q)
+    E = np.zeros_like(Q)
+    E[:12, :12] = np.eye(12)
+    assert np.array_equal(W, Q - E)
+    F = np.eye(90) - W @ Y.T
+    assert np.linalg.norm(F.T @ F - np.eye(90)) < 1e-13
+    assert np.max(np.abs(F[:, :12] - Q)) < 1e-14
+    q = la_inputs.gaussian((20, 1), 706).astype(np.float64)
+    q /= np.linalg.norm(q)
+    W, Y = orc.yamamoto(q)
+    v = q[:, 0] - np.eye(20)[:, 0]
+    assert np.max(np.abs(np.eye(20) - W @ Y.T - (np.eye(20) - 2 * np.outer(v, v) / (v @ v)))) < 1e-14
+
+
+def pin_qr_caqr(orc):
+    """Algorithm caqr: A = Q R with orthonormal Q and the same R (up to row
+    signs) as LAPACK, for several panel widths and block heights; one panel
+    gives exactly the R of tsqr."""
+    A = la_inputs.gaussian((200, 48), 707).astype(np.float64)
+    for b, mr in ((8, 64), (16, 50), (12, 48), (48, 100)):
+        Q, R = orc.caqr(A, b, mr)
+        _check_qr(A, Q, R)
+        _, R2 = orc.caqr(A, b, mr, want_q=False)
+        assert np.array_equal(R, R2)
+    _, Rt = orc.tsqr(A, 64)
+    _, Rc = orc.caqr(A, 48, 64)
+    assert np.array_equal(Rt, Rc)
+    S = la_inputs.gaussian((40, 40), 708).astype(np.float64)
+    _check_qr(S, *orc.caqr(S, 8, 16))
+
+
 ALL_PINS = [
     pin_paper_iteration_counts,
     pin_scalar_map_properties,
@@ -504,4 +594,9 @@ ALL_PINS = [
     pin_matfunc_cheb_nonsymmetric,
     pin_matfunc_cheb_low_degree,
     pin_matfunc_cheb_exponential,
+    pin_qr_2x2_golden,
+    pin_qr_householder_vs_numpy,
+    pin_qr_tsqr,
+    pin_qr_yamamoto,
+    pin_qr_caqr,
 ]

@@ -53,6 +53,28 @@ MUTANTS = {
                         "(A[i * lda + j] - (i == j ? lo : 0.0)) / w;"),
     "cheb_first_term": ("F[i * ldf + j] += c[1] * Tc[i * n + j];",
                         "F[i * ldf + j] += c[1] * Tp[i * n + j];"),
+    "hh_beta_sign": ("const double beta = x0 >= 0.0 ? -nrm : nrm;",
+                     "const double beta = x0 >= 0.0 ? nrm : -nrm;"),
+    "hh_tau": ("tau[j] = (beta - x0) / beta;", "tau[j] = (x0 - beta) / beta;"),
+    "hh_drop_unit_term": ("            double d = W[j * n + c];", "            double d = 0.0;"),
+    "hh_q_forward_order": ("        for (int64_t j = n - 1; j >= 0; --j) {\n            if (tau[j] == 0.0)",
+                           "        for (int64_t j = 0; j < n; ++j) {\n            if (tau[j] == 0.0)"),
+    "tsqr_halves_swapped": ("const double *H = Qp + (half ? n * n : 0);",
+                            "const double *H = Qp + (half ? 0 : n * n);"),
+    "tsqr_stack_same_r": ("S[(n + i) * n + j] = Rs[b * n * n + i * n + j];",
+                          "S[(n + i) * n + j] = Rs[a * n * n + i * n + j];"),
+    "tsqr_group_end": ("const int64_t end = (b + g < p) ? b + g : p;",
+                       "const int64_t end = (b + 1 < p) ? b + 1 : p;"),
+    "yamamoto_printed_t": ("M[i * n + j] = ((i == j) ? 1.0 : 0.0) - Q[j * ldq + i];",
+                           "M[i * n + j] = ((i == j) ? 1.0 : 0.0) - Q[i * ldq + j];"),
+    "yamamoto_w_sign": ("W[i * ldw + j] = Q[i * ldq + j] - ((i == j) ? 1.0 : 0.0);",
+                        "W[i * ldw + j] = Q[i * ldq + j] + ((i == j) ? 1.0 : 0.0);"),
+    "caqr_update_sign": ("orc_gemm(0, 0, ml, nr, b, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);",
+                         "orc_gemm(0, 0, ml, nr, b, 1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);"),
+    "caqr_applies_q_not_qt": ("orc_gemm(1, 0, b, nr, ml, 1.0, W, n, X + c * n + c + b, n, 0.0, Z, nr);",
+                              "orc_gemm(1, 0, b, nr, ml, 1.0, Y, n, X + c * n + c + b, n, 0.0, Z, nr);"),
+    "caqr_q_forward_order": ("for (int64_t jp = np - 1; jp >= 0; --jp) {",
+                             "for (int64_t jp = 0; jp < np; ++jp) {"),
 }
 
 
