@@ -723,16 +723,17 @@ int orc_yamamoto(int64_t m, int64_t n, const double *Q, int64_t ldq, double *W,
  * columns to the right are replaced by Q_f^T A_r = A_r - Y (W^T A_r).  R
  * (n x n, ldr) is the upper triangle of the result; Q (m x n, ldq, may be
  * NULL) is the reduced Q factor, Q_f(0) Q_f(1) ... [I_n; 0] with each Q_f
- * acting on rows c:.  n must be a multiple of b.  Returns 0, -1, or -3 (a
- * singular I - Q_1).
+ * acting on rows c:.  When b does not divide n the last panel has the
+ * remaining n mod b columns.  Returns 0, -1, or -3 (a singular I - Q_1).
  */
 int orc_caqr(int64_t m, int64_t n, const double *A, int64_t lda, int64_t b, int64_t mr,
              double *Q, int64_t ldq, double *R, int64_t ldr)
 {
-    if (m < n || n < 1 || b < 1 || n % b != 0 || mr < b || lda < n || ldr < n ||
-        (Q && ldq < n))
+    if (m < n || n < 1 || b < 1 || mr < b || lda < n || ldr < n || (Q && ldq < n))
         return -1;
-    const int64_t np = n / b;
+    if (b > n)
+        b = n;
+    const int64_t np = (n + b - 1) / b;
     double *X = (double *)malloc(sizeof(double) * (size_t)(m * n));
     double *Qr = (double *)malloc(sizeof(double) * (size_t)(m * b));
     double *Rr = (double *)malloc(sizeof(double) * (size_t)(b * b));
@@ -749,24 +750,26 @@ int orc_caqr(int64_t m, int64_t n, const double *A, int64_t lda, int64_t b, int6
             X[i * n + j] = A[i * lda + j];
     int rc = 0;
     for (int64_t jp = 0; jp < np && rc == 0; ++jp) {
-        const int64_t c = jp * b, ml = m - c, nr = n - c - b;
-        double *W = Ws + c * n + c;   /* W of panel jp: rows c.., columns c..c+b (ld n) */
+        const int64_t c = jp * b, ml = m - c;
+        const int64_t nc = (n - c < b) ? n - c : b;   /* the last panel may be narrower */
+        const int64_t nr = n - c - nc;
+        double *W = Ws + c * n + c;   /* W of panel jp: rows c.., columns c..c+nc (ld n) */
         double *Y = Ys + c * n + c;
         for (int64_t i = 0; i < ml; ++i)
-            for (int64_t j = 0; j < b; ++j)
-                Ac[i * b + j] = X[(c + i) * n + c + j];
-        rc = orc_tsqr(ml, b, Ac, b, mr < ml ? mr : ml, Qr, b, Rr, b);
+            for (int64_t j = 0; j < nc; ++j)
+                Ac[i * nc + j] = X[(c + i) * n + c + j];
+        rc = orc_tsqr(ml, nc, Ac, nc, mr < ml ? mr : ml, Qr, nc, Rr, nc);
         if (rc == 0)
-            rc = orc_yamamoto(ml, b, Qr, b, W, n, Y, n);
+            rc = orc_yamamoto(ml, nc, Qr, nc, W, n, Y, n);
         if (rc != 0)
             break;
         for (int64_t i = 0; i < ml; ++i)
-            for (int64_t j = 0; j < b; ++j)
-                X[(c + i) * n + c + j] = i < b ? Rr[i * b + j] : 0.0;
+            for (int64_t j = 0; j < nc; ++j)
+                X[(c + i) * n + c + j] = i < nc ? Rr[i * nc + j] : 0.0;
         if (nr > 0) {
-            /* Z = W^T A_r (b x nr);  A_r <- A_r - Y Z */
-            orc_gemm(1, 0, b, nr, ml, 1.0, W, n, X + c * n + c + b, n, 0.0, Z, nr);
-            orc_gemm(0, 0, ml, nr, b, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);
+            /* Z = W^T A_r (nc x nr);  A_r <- A_r - Y Z */
+            orc_gemm(1, 0, nc, nr, ml, 1.0, W, n, X + c * n + c + nc, n, 0.0, Z, nr);
+            orc_gemm(0, 0, ml, nr, nc, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + nc, n);
         }
     }
     if (rc == 0) {
@@ -780,10 +783,11 @@ int orc_caqr(int64_t m, int64_t n, const double *A, int64_t lda, int64_t b, int6
                     Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
             for (int64_t jp = np - 1; jp >= 0; --jp) {
                 const int64_t c = jp * b, ml = m - c;
+                const int64_t nc = (n - c < b) ? n - c : b;
                 const double *W = Ws + c * n + c, *Y = Ys + c * n + c;
                 /* Q[c:, :] <- Q[c:, :] - W (Y^T Q[c:, :]) */
-                orc_gemm(1, 0, b, n, ml, 1.0, Y, n, Q + c * ldq, ldq, 0.0, Z, n);
-                orc_gemm(0, 0, ml, n, b, -1.0, W, n, Z, n, 1.0, Q + c * ldq, ldq);
+                orc_gemm(1, 0, nc, n, ml, 1.0, Y, n, Q + c * ldq, ldq, 0.0, Z, n);
+                orc_gemm(0, 0, ml, n, nc, -1.0, W, n, Z, n, 1.0, Q + c * ldq, ldq);
             }
         }
     }

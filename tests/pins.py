@@ -553,10 +553,11 @@ def pin_qr_yamamoto(orc):
 
 def pin_qr_caqr(orc):
     """Algorithm caqr: A = Q R with orthonormal Q and the same R (up to row
-    signs) as LAPACK, for several panel widths and block heights; one panel
-    gives exactly the R of tsqr."""
+    signs) as LAPACK, for several panel widths (some not dividing n, so the
+    last panel is narrower) and block heights; one panel gives exactly the R
+    of tsqr."""
     A = la_inputs.gaussian((200, 48), 707).astype(np.float64)
-    for b, mr in ((8, 64), (16, 50), (12, 48), (48, 100)):
+    for b, mr in ((8, 64), (16, 50), (12, 48), (48, 100), (20, 64), (7, 30)):
         Q, R = orc.caqr(A, b, mr)
         _check_qr(A, Q, R)
         _, R2 = orc.caqr(A, b, mr, want_q=False)

@@ -69,10 +69,12 @@ MUTANTS = {
                            "M[i * n + j] = ((i == j) ? 1.0 : 0.0) - Q[i * ldq + j];"),
     "yamamoto_w_sign": ("W[i * ldw + j] = Q[i * ldq + j] - ((i == j) ? 1.0 : 0.0);",
                         "W[i * ldw + j] = Q[i * ldq + j] + ((i == j) ? 1.0 : 0.0);"),
-    "caqr_update_sign": ("orc_gemm(0, 0, ml, nr, b, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);",
-                         "orc_gemm(0, 0, ml, nr, b, 1.0, Y, n, Z, nr, 1.0, X + c * n + c + b, n);"),
-    "caqr_applies_q_not_qt": ("orc_gemm(1, 0, b, nr, ml, 1.0, W, n, X + c * n + c + b, n, 0.0, Z, nr);",
-                              "orc_gemm(1, 0, b, nr, ml, 1.0, Y, n, X + c * n + c + b, n, 0.0, Z, nr);"),
+    "caqr_update_sign": ("orc_gemm(0, 0, ml, nr, nc, -1.0, Y, n, Z, nr, 1.0, X + c * n + c + nc, n);",
+                         "orc_gemm(0, 0, ml, nr, nc, 1.0, Y, n, Z, nr, 1.0, X + c * n + c + nc, n);"),
+    "caqr_applies_q_not_qt": ("orc_gemm(1, 0, nc, nr, ml, 1.0, W, n, X + c * n + c + nc, n, 0.0, Z, nr);",
+                              "orc_gemm(1, 0, nc, nr, ml, 1.0, Y, n, X + c * n + c + nc, n, 0.0, Z, nr);"),
+    "caqr_drops_last_panel": ("const int64_t np = (n + b - 1) / b;\n    double *X",
+                              "const int64_t np = n / b;\n    double *X"),
     "caqr_q_forward_order": ("for (int64_t jp = np - 1; jp >= 0; --jp) {",
                              "for (int64_t jp = 0; jp < np; ++jp) {"),
 }
