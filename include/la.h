@@ -51,7 +51,8 @@ typedef enum {
     LA_ERR_QUEUE_FULL = 7,     /* serving queue at capacity                      */
     LA_ERR_TOO_LARGE = 8,      /* request footprint exceeds the serving arena    */
     LA_ERR_NOT_READY = 9,      /* serving request still pending                  */
-    LA_ERR_UNKNOWN_REQUEST = 10
+    LA_ERR_UNKNOWN_REQUEST = 10,
+    LA_ERR_BREAKDOWN = 11      /* I - Q_1 singular or nearly so (eq. Yamamoto)   */
 } la_status;
 
 /* Arithmetic of the GEMM products.  All paths read and write FP32 and
@@ -271,6 +272,63 @@ la_status la_matfunc_cheb(la_context *ctx, int64_t n, const float *A, int64_t ld
                           double hi, const double *coef, int ncoef, float *F, int64_t ldf,
                           void *workspace, size_t ws_bytes, la_precision prec,
                           void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * QR factorisation (section III.B): Algorithm tsqr, the WY form of
+ * eq. (Yamamoto) and Algorithm caqr.  Matrices are FP32 row-major in device
+ * memory; workspaces are device memory, 256-byte aligned, of at least the
+ * size the matching *_workspace_size() returns (0 for a shape the call
+ * rejects).  Each call runs on hip_stream and returns after its last kernel
+ * has completed.  The local factorisations are Householder reflections in
+ * FP32 with FP64 column norms; R_jj takes the sign opposite to the pivot
+ * entry it replaces, so R's diagonal signs depend on the tree and may differ
+ * from another QR of the same matrix (QR is unique up to those signs).
+ * ---------------------------------------------------------------------- */
+
+/* Algorithm tsqr: reduced QR of an m x n A (1 <= n <= 128, m >= n; lda,
+ * ldq, ldr >= n): Q (m x n, orthonormal columns) and R (n x n, upper
+ * triangular, zeros below the diagonal) with A = Q R.  The rows are split
+ * into blocks of at most 256 rows, each factored in one workgroup; the
+ * blocks' R factors are stacked and factored again until one remains, and
+ * the Q factors are multiplied down the tree.  A, Q, R and the workspace
+ * must not overlap. */
+size_t la_tsqr_workspace_size(int64_t m, int64_t n);
+la_status la_tsqr(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda, float *Q,
+                  int64_t ldq, float *R, int64_t ldr, void *workspace, size_t ws_bytes,
+                  void *hip_stream);
+
+/* eq. (Yamamoto): for a reduced Q (m x n, 1 <= n <= 128, m >= n), W = Q -
+ * [I_n; 0] and Y = W (I - Q_1)^-1 with Q_1 the first n rows of Q, both
+ * m x n, so that Q_f = I - W Y^T is orthogonal with Q_f [I_n; 0] = Q.  (The
+ * equation's T^-1 = I - Q_1 is read as its transpose: only that makes the
+ * first n columns of Q_f equal Q.)  The inverse is formed by Gauss-Jordan
+ * elimination with partial pivoting in FP64.  LA_ERR_BREAKDOWN if a pivot
+ * falls below 2^-16 in magnitude or is not finite (W and Y are then
+ * unreliable): the breakdown the method has when Q_1 is close to a matrix
+ * with eigenvalue 1.  Q, W, Y and the workspace must not overlap. */
+size_t la_wy_workspace_size(int64_t n);
+la_status la_wy(la_context *ctx, int64_t m, int64_t n, const float *Q, int64_t ldq, float *W,
+                int64_t ldw, float *Y, int64_t ldy, void *workspace, size_t ws_bytes,
+                void *hip_stream);
+
+/* Algorithm caqr (right-looking): QR of an m x n A (m >= n, lda >= n) in
+ * place, in panels of `panel` columns (1..128; the last panel takes the
+ * remainder).  Each panel A_l: la_tsqr, la_wy, A_l <- [R; 0], and the
+ * columns to its right A_r <- Q_f^T A_r = A_r - Y (W^T A_r) by two GEMM
+ * launches of precision prec (AUTO = BF16X6: the second product's K is the
+ * panel width, too short for BF16X3's per-term error of about 2^-16 to
+ * average out to FP32 level).  On return the first n rows
+ * of A hold R (upper triangle; zeros below) and the rows below are zero.  If
+ * Q is not NULL (ldq >= n) it receives the reduced Q factor
+ * Q_f(0) Q_f(1) ... [I_n; 0] (m x n), formed after the last panel by the
+ * same two-launch update per panel in reverse order; the workspace then
+ * also keeps every panel's W and Y (2 m n floats).  LA_ERR_BREAKDOWN as for
+ * la_wy (A then holds a partial result).  A, Q and the workspace must not
+ * overlap. */
+size_t la_caqr_workspace_size(int64_t m, int64_t n, int panel, int want_q);
+la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, float *Q,
+                  int64_t ldq, int panel, void *workspace, size_t ws_bytes, la_precision prec,
+                  void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of polar requests.

@@ -18,7 +18,8 @@ from ._binding import (InverseInfo, LAError, PolarInfo, PolarOpts, Precision, Se
                        LIB_PATH, SIGNATURES)
 
 __all__ = ["gemm", "gemm_ws", "gemm_workspace_size", "pack_bf16x3", "gemm_packed", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
-           "matfunc_odd", "matfunc_cheb", "Precision", "LAError", "Status", "lib", "LIB_PATH",
+           "matfunc_odd", "matfunc_cheb", "tsqr", "wy", "caqr", "caqr_workspace_size",
+           "Precision", "LAError", "Status", "lib", "LIB_PATH",
            "Server"]
 
 
@@ -265,6 +266,75 @@ def matfunc_cheb(A: torch.Tensor, lo: float, hi: float, coef, *, F: torch.Tensor
     check(lib().la_matfunc_cheb(ctx, n, pa, lda, float(lo), float(hi), cp, len(c), pf, ldf, wp,
                                 avail, int(prec), _stream_ptr(stream)))
     return F
+
+
+def _workspace(workspace, need, dev):
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wp = workspace.data_ptr()
+    wp_al = (wp + 255) & ~255
+    return workspace, wp_al, max(workspace.numel() - (wp_al - wp), 0)
+
+
+def _ctx(t: torch.Tensor):
+    return context(t.device.index if t.device.index is not None else torch.cuda.current_device())
+
+
+def _row_major(A: torch.Tensor, name: str):
+    pa, m, n, lda, ta = _as_matrix(A, name)
+    if ta:
+        A = A.contiguous()
+        pa, m, n, lda, ta = _as_matrix(A, name)
+    return A, pa, m, n, lda
+
+
+def tsqr(A: torch.Tensor, *, workspace: torch.Tensor | None = None, stream=None):
+    """Reduced QR (Q m x n, R n x n) of an m x n A (n <= 128) through ``la_tsqr``
+    (Algorithm tsqr)."""
+    A, pa, m, n, lda = _row_major(A, "A")
+    Q = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    R = torch.empty((n, n), dtype=torch.float32, device=A.device)
+    workspace, wp, avail = _workspace(workspace, int(lib().la_tsqr_workspace_size(m, n)), A.device)
+    check(lib().la_tsqr(_ctx(A), m, n, pa, lda, Q.data_ptr(), n, R.data_ptr(), n, wp, avail,
+                        _stream_ptr(stream)))
+    return Q, R
+
+
+def wy(Q: torch.Tensor, *, workspace: torch.Tensor | None = None, stream=None):
+    """W = Q - [I; 0] and Y = W (I - Q_1)^-1 of a reduced Q (m x n, n <= 128)
+    through ``la_wy`` (eq. Yamamoto): I - W Y^T is orthogonal with first n columns Q."""
+    Q, pq, m, n, ldq = _row_major(Q, "Q")
+    W = torch.empty((m, n), dtype=torch.float32, device=Q.device)
+    Y = torch.empty((m, n), dtype=torch.float32, device=Q.device)
+    workspace, wp, avail = _workspace(workspace, int(lib().la_wy_workspace_size(n)), Q.device)
+    check(lib().la_wy(_ctx(Q), m, n, pq, ldq, W.data_ptr(), n, Y.data_ptr(), n, wp, avail,
+                      _stream_ptr(stream)))
+    return W, Y
+
+
+def caqr_workspace_size(m: int, n: int, panel: int = 64, want_q: bool = True) -> int:
+    return int(lib().la_caqr_workspace_size(m, n, panel, int(want_q)))
+
+
+def caqr(A: torch.Tensor, *, panel: int = 64, want_q: bool = True, inplace: bool = False,
+         prec: Precision = Precision.AUTO, workspace: torch.Tensor | None = None, stream=None):
+    """QR of an m x n A (m >= n) through ``la_caqr`` (Algorithm caqr).  Returns
+    (Q or None, R) with R the n x n upper triangle; the factorisation runs in
+    place on A when ``inplace`` (A must then be row-major), else on a copy."""
+    if inplace:
+        pa, m, n, lda, ta = _as_matrix(A, "A")
+        if ta:
+            raise ValueError("inplace needs a row-major A")
+        X = A
+    else:
+        X = A.contiguous().clone()
+        pa, m, n, lda, _ = _as_matrix(X, "A")
+    Q = torch.empty((m, n), dtype=torch.float32, device=A.device) if want_q else None
+    workspace, wp, avail = _workspace(workspace, caqr_workspace_size(m, n, panel, want_q),
+                                      A.device)
+    check(lib().la_caqr(_ctx(A), m, n, pa, lda, Q.data_ptr() if want_q else None, n, panel, wp,
+                        avail, int(prec), _stream_ptr(stream)))
+    return Q, X[:n]
 
 
 from .serve import Server  # noqa: E402

@@ -38,6 +38,7 @@ class Status(enum.IntEnum):
     TOO_LARGE = 8
     NOT_READY = 9
     UNKNOWN_REQUEST = 10
+    BREAKDOWN = 11
 
 
 class LAError(RuntimeError):
@@ -157,6 +158,15 @@ SIGNATURES = {
     "la_matfunc_cheb": (ctypes.c_int, [_VP, _I64, _VP, _I64, ctypes.c_double, ctypes.c_double,
                                        _VP, ctypes.c_int, _VP, _I64, _VP, ctypes.c_size_t,
                                        ctypes.c_int, _VP]),
+    "la_tsqr_workspace_size": (ctypes.c_size_t, [_I64, _I64]),
+    "la_tsqr": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
+                               ctypes.c_size_t, _VP]),
+    "la_wy_workspace_size": (ctypes.c_size_t, [_I64]),
+    "la_wy": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
+                             ctypes.c_size_t, _VP]),
+    "la_caqr_workspace_size": (ctypes.c_size_t, [_I64, _I64, ctypes.c_int, ctypes.c_int]),
+    "la_caqr": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, ctypes.c_int, _VP,
+                               ctypes.c_size_t, ctypes.c_int, _VP]),
     "la_serve_create": (ctypes.c_int, [_VP, ctypes.POINTER(ServeConfig), _VP, ctypes.c_size_t,
                                        ctypes.POINTER(_VP)]),
     "la_serve_submit": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, ctypes.POINTER(PolarOpts),

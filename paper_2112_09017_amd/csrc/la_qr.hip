@@ -1,0 +1,1015 @@
+// QR factorisation (section III.B of arXiv 2112.09017) on one GPU.
+//
+// la_tsqr -- Algorithm tsqr for an m x n panel, n <= 128.  The rows are cut
+//            into blocks of at most 256 rows (each with at least n rows).
+//            One workgroup factors one block by Householder reflections with
+//            the block resident in LDS, writes its R and forms its Q in place.
+//            The R factors are stacked and factored again the same way (a
+//            256-row block holds 256 / n of them, so the tree reduces by that
+//            factor per level rather than pairwise) until one R remains.  The
+//            Q factors are then multiplied down the tree: every row of a
+//            level's Q times the n x n slice of the level above that belongs
+//            to its block.
+// la_wy   -- eq. (Yamamoto): W = Q - [I; 0] and Y = W (I - Q_1)^-1, the
+//            inverse by Gauss-Jordan elimination with partial pivoting in FP64
+//            in one workgroup, then one row-parallel product.
+// la_caqr -- Algorithm caqr (right-looking): per panel of b columns, la_tsqr,
+//            la_wy, A_l <- [R; 0] and A_r <- A_r - Y (W^T A_r) as two GEMM
+//            launches (the first split along its long K = rows dimension);
+//            optionally Q = Q_f(0) ... Q_f(last) [I; 0] afterwards.  AUTO runs
+//            the products as 6xBF16: the update's K is only the panel width,
+//            too short for the 3xBF16 products' per-term error (about 2^-16
+//            relative) to average out.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "la_internal.h"
+
+namespace la {
+namespace {
+
+constexpr int kRows = 256;        // rows of one local factorisation
+constexpr int kQrThreads = 512;
+constexpr int kMaxPanel = 128;
+constexpr int kMaxLevels = 40;
+constexpr int kMaxSplits = 16;
+// A Gauss-Jordan pivot of I - Q_1 below this magnitude is reported as the
+// breakdown of eq. (Yamamoto): Y would carry errors of order u / pivot.
+constexpr double kPivotFloor = 1.0 / 65536.0;
+
+// Row partition of a tall matrix into blocks of 256 rows.  When the last
+// block would hold fewer than nc rows, the last two blocks share their rows
+// evenly (at least 128 >= nc each), so every block has at least nc rows.
+struct Part {
+    int64_t rows;
+    int64_t last_start;
+    int nb;
+};
+
+__host__ __device__ inline Part make_part(int64_t rows, int nc)
+{
+    Part p;
+    p.rows = rows;
+    const int64_t nb = (rows + kRows - 1) / kRows;
+    p.nb = (int)nb;
+    const int64_t rem = rows - kRows * (nb - 1);
+    p.last_start = (nb > 1 && rem < nc) ? kRows * (nb - 2) + (kRows + rem) / 2 : kRows * (nb - 1);
+    return p;
+}
+
+__host__ __device__ inline int64_t part_start(const Part &p, int64_t i)
+{
+    if (i >= p.nb)
+        return p.rows;
+    return i == p.nb - 1 ? p.last_start : kRows * i;
+}
+
+__host__ __device__ inline int64_t part_block(const Part &p, int64_t r)
+{
+    return r >= p.last_start ? p.nb - 1 : r / kRows;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// Householder QR of one row block (rows x nc, rows <= 256, nc <= B) per
+// workgroup, with the block resident in registers: thread (c, g) holds
+// column c over the RPG rows of group g.  Reflection j uses u = x - beta e_j
+// (x = column j from row j down, beta = -sign(x_j) ||x||) unscaled, and
+// H_j = I - kappa u u^T with kappa = 1 / (beta (beta - x_j)); column j keeps
+// x below the diagonal, u_j and kappa go to LDS arrays.  The owners of the
+// next column publish it to LDS (ubuf) after each update, with FP64 partial
+// sums of its squares below the diagonal (four FP32 squares at a time), so
+// every step is: norm and reflection from the published column, partial dot
+// products u^T x_c per group, one barrier, the rank-1 update, one barrier.
+// Row chunks above the diagonal are skipped.  R (row block blk of R, ld ldr)
+// is written from the registers; then Q = H_0 ... H_{nc-1} [I; 0] is formed
+// in place, last reflection first (column j becomes H_j e_j once the columns
+// to its right hold H_{j+1} ... e_c), and written to Q (ldq).  X may equal Q.
+template <int B>
+__global__ __launch_bounds__(kQrThreads) void qr_block_kernel(const float *X, int64_t ldx,
+                                                              Part part, int nc, float *Q,
+                                                              int64_t ldq, float *R, int64_t ldr)
+{
+    constexpr int G = kQrThreads / B;
+    constexpr int RPG = kRows / G;
+    constexpr int PD = G + 4;   // row stride of pdot (16-byte multiple)
+    static_assert(RPG % 4 == 0 && G % 4 == 0, "groups are handled four rows at a time");
+    static_assert(B % 64 == 0, "a wave must not straddle two row groups");
+    __shared__ __attribute__((aligned(16))) float ubuf[kRows];
+    __shared__ __attribute__((aligned(16))) float pdot[B * PD];
+    __shared__ double psq[G];
+    __shared__ float s_u0[B], s_kap[B], s_beta[B];
+
+    const int t = threadIdx.x;
+    // B >= 64: every wave lies in one row group, so g (and the row-chunk
+    // tests below) are wave-uniform
+    const int c = t % B, g = __builtin_amdgcn_readfirstlane(t / B);
+    const int64_t blk = blockIdx.x;
+    const int64_t r0 = part_start(part, blk);
+    const int rows = (int)(part_start(part, blk + 1) - r0);
+    const int rlo = g * RPG;
+    nc = __builtin_amdgcn_readfirstlane(nc);
+    const bool col = c < nc;
+
+    float f[RPG], u[RPG];
+#pragma unroll
+    for (int i = 0; i < RPG; ++i)
+        f[i] = (col && rlo + i < rows) ? X[(r0 + rlo + i) * ldx + c] : 0.0f;
+
+    // column of this thread -> ubuf; FP64 partial sum of squares of rows > lim
+    auto publish = [&](int lim) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPG; i += 4) {
+            *(float4 *)&ubuf[rlo + i] = make_float4(f[i], f[i + 1], f[i + 2], f[i + 3]);
+            float q = 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (rlo + i + e > lim)
+                    q = fmaf(f[i + e], f[i + e], q);
+            s += (double)q;
+        }
+        psq[g] = s;
+    };
+
+    if (c == 0)
+        publish(0);
+    __syncthreads();
+
+    for (int jv = 0; jv < nc; ++jv) {
+        // the step index is the same in every lane: keep it (and every row
+        // chunk test derived from it) scalar
+        const int j = __builtin_amdgcn_readfirstlane(jv);
+        double sig = 0.0;
+        for (int q = 0; q < G; ++q)
+            sig += psq[q];
+        const double x0 = ubuf[j];
+        const double nrm = sqrt(x0 * x0 + sig);
+        float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
+        if (nrm > 0.0) {
+            const double bt = x0 >= 0.0 ? -nrm : nrm;
+            u0 = (float)(x0 - bt);
+            kap = (float)(1.0 / (bt * (bt - x0)));
+            beta = (float)bt;
+        }
+        if (t == 0) {
+            s_u0[j] = u0;
+            s_kap[j] = kap;
+            s_beta[j] = beta;
+        }
+        const bool act = col && c > j;
+        float d = 0.0f;
+        if (act) {
+            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < RPG; i += 4) {
+                if (rlo + i > j) {
+                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
+                    u[i] = uv.x;
+                    u[i + 1] = uv.y;
+                    u[i + 2] = uv.z;
+                    u[i + 3] = uv.w;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
+                } else if (rlo + i + 3 >= j) {
+                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
+                    const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = rlo + i + e;
+                        u[i + e] = r < j ? 0.0f : (r == j ? u0 : ua[e]);
+                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
+                    }
+                }
+            }
+            d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+        }
+        pdot[c * PD + g] = d;
+        __syncthreads();
+        if (act) {
+            float w = 0.0f;
+#pragma unroll
+            for (int q = 0; q < G; q += 4) {
+                const float4 p = *(const float4 *)&pdot[c * PD + q];
+                w += p.x;
+                w += p.y;
+                w += p.z;
+                w += p.w;
+            }
+            const float sc = kap * w;
+#pragma unroll
+            for (int i = 0; i < RPG; i += 4)
+                if (rlo + i + 3 >= j) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        f[i + e] = fmaf(-sc, u[i + e], f[i + e]);
+                }
+            if (c == j + 1)
+                publish(j + 1);
+        }
+        __syncthreads();
+    }
+
+    float *Rb = R + blk * nc * ldr;
+#pragma unroll
+    for (int i = 0; i < RPG; ++i) {
+        const int rr = rlo + i;
+        if (col && rr < nc)
+            Rb[(int64_t)rr * ldr + c] = c > rr ? f[i] : (c == rr ? s_beta[rr] : 0.0f);
+    }
+
+    if (c == nc - 1)
+        publish(kRows);
+    __syncthreads();
+    for (int jv = nc - 1; jv >= 0; --jv) {
+        const int j = __builtin_amdgcn_readfirstlane(jv);
+        const float u0 = s_u0[j], kap = s_kap[j];
+        const bool upd = col && c > j;
+        const bool form = c == j;
+        float d = 0.0f;
+        if (upd || form) {
+            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < RPG; i += 4) {
+                if (rlo + i > j) {
+                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
+                    u[i] = uv.x;
+                    u[i + 1] = uv.y;
+                    u[i + 2] = uv.z;
+                    u[i + 3] = uv.w;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
+                } else if (form || rlo + i + 3 >= j) {
+                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
+                    const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = rlo + i + e;
+                        u[i + e] = r < j ? 0.0f : (r == j ? u0 : ua[e]);
+                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
+                    }
+                }
+            }
+            d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+        }
+        pdot[c * PD + g] = d;
+        __syncthreads();
+        if (upd) {
+            float w = 0.0f;
+#pragma unroll
+            for (int q = 0; q < G; q += 4) {
+                const float4 p = *(const float4 *)&pdot[c * PD + q];
+                w += p.x;
+                w += p.y;
+                w += p.z;
+                w += p.w;
+            }
+            const float sc = kap * w;
+#pragma unroll
+            for (int i = 0; i < RPG; i += 4)
+                if (rlo + i + 3 >= j) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        f[i + e] = fmaf(-sc, u[i + e], f[i + e]);
+                }
+        } else if (form) {
+            // column j = H_j e_j = e_j - kappa u_j u (zero above row j)
+            const float s2 = kap * u0;
+#pragma unroll
+            for (int i = 0; i < RPG; ++i) {
+                const int r = rlo + i;
+                f[i] = r < j ? 0.0f : fmaf(-s2, u[i], r == j ? 1.0f : 0.0f);
+            }
+        }
+        if (c == j - 1)
+            publish(kRows);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < RPG; ++i)
+        if (col && rlo + i < rows)
+            Q[(r0 + rlo + i) * ldq + c] = f[i];
+}
+
+// out[r, :] = (in[r, :] - sub [r < nc] e_r^T) M_b for every row r < part.rows,
+// with M_b = Mb + b * nc * nc (nc x nc, ld nc) for the partition block b
+// holding row r, or M_0 for every row when single; wout (optional) receives
+// in[r, :] - sub e_r^T.  Workgroup (b, y) takes rows 32 y .. 32 y + 31 of
+// block b, staged in LDS with M_b; 8 threads per row, each forming B / 8 of
+// its outputs.  out may equal in: every row is read whole before any
+// thread of the workgroup writes.
+template <int B>
+__global__ __launch_bounds__(256) void rowmul_kernel(const float *in, int64_t ldi, Part part,
+                                                     int single, int nc,
+                                                     const float *__restrict__ Mb, float *out,
+                                                     int64_t ldo, float *wout, int64_t ldw,
+                                                     int sub)
+{
+    constexpr int CG = 8, CPT = B / CG, RPB = 256 / CG;
+    __shared__ float xs[RPB * (B + 1)];
+    __shared__ __attribute__((aligned(16))) float ms[B * B];
+    const int t = threadIdx.x, rr = t / CG, cg = t % CG;
+    const int64_t b = blockIdx.x;
+    const int64_t rbase = part_start(part, b) + (int64_t)blockIdx.y * RPB;
+    const int64_t rend = part_start(part, b + 1);
+    if (rbase >= rend)
+        return;
+    const float *M = Mb + (single ? 0 : b * nc * nc);
+    for (int idx = t; idx < nc * nc; idx += 256)
+        ms[(idx / nc) * B + idx % nc] = M[idx];
+    for (int idx = t; idx < RPB * B; idx += 256) {
+        const int i = idx / B, k = idx % B;
+        const int64_t r = rbase + i;
+        float v = 0.0f;
+        if (r < rend && k < nc) {
+            v = in[r * ldi + k];
+            if (sub && r == k)
+                v -= 1.0f;
+            if (wout)
+                wout[r * ldw + k] = v;
+        }
+        xs[i * (B + 1) + k] = v;
+    }
+    __syncthreads();
+    const int64_t r = rbase + rr;
+    if (r >= rend)
+        return;
+    float acc[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e)
+        acc[e] = 0.0f;
+    for (int k = 0; k < nc; ++k) {
+        const float xv = xs[rr * (B + 1) + k];
+#pragma unroll
+        for (int e = 0; e < CPT; e += 4) {
+            const float4 mv = *(const float4 *)&ms[k * B + cg * CPT + e];
+            acc[e] = fmaf(xv, mv.x, acc[e]);
+            acc[e + 1] = fmaf(xv, mv.y, acc[e + 1]);
+            acc[e + 2] = fmaf(xv, mv.z, acc[e + 2]);
+            acc[e + 3] = fmaf(xv, mv.w, acc[e + 3]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e)
+        if (cg * CPT + e < nc)
+            out[r * ldo + cg * CPT + e] = acc[e];
+}
+
+// Minv = (I - Q_1)^-1 for the top nc x nc block Q_1 of Q (ld ldq), by
+// Gauss-Jordan elimination with partial pivoting in FP64 in LDS; rounded to
+// FP32 (nc x nc, ld nc).  flag[0] = 1 if a pivot is below kPivotFloor in
+// magnitude or not finite.  The row interchanges are undone by writing
+// column i of the eliminated array to column rowidx[i] of the inverse.
+template <int B>
+__global__ __launch_bounds__(512) void wy_inverse_kernel(const float *__restrict__ Q, int64_t ldq,
+                                                         int nc, float *__restrict__ Minv,
+                                                         int *flag)
+{
+    constexpr int LD = B + 1;
+    constexpr int RP = 512 / B;   // rows handled at a time: thread (i0, cc) takes rows i0 + RP q
+    __shared__ double M[B * LD];
+    __shared__ double fcol[B];
+    __shared__ int piv[B];
+    __shared__ int rowidx[B];
+    const int t = threadIdx.x;
+    const int cc = t % B, i0 = t / B;
+    const bool ccol = cc < nc;
+    for (int i = i0; i < nc; i += RP)
+        if (ccol)
+            M[i * LD + cc] = (i == cc ? 1.0 : 0.0) - (double)Q[(int64_t)i * ldq + cc];
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+        if (t < 64) {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + t; i < nc; i += 64) {
+                const double a = fabs(M[i * LD + k]);
+                if (a > best) {
+                    best = a;
+                    bi = i;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (t == 0)
+                piv[k] = bi;
+        }
+        __syncthreads();
+        const int p = piv[k];
+        if (p != k && t < nc) {
+            const double tmp = M[k * LD + t];
+            M[k * LD + t] = M[p * LD + t];
+            M[p * LD + t] = tmp;
+        }
+        __syncthreads();
+        const double pv = M[k * LD + k];
+        const double inv = 1.0 / pv;
+        if (t == 0 && !(fabs(pv) >= kPivotFloor && isfinite(pv)))
+            flag[0] = 1;
+        if (t < nc)
+            fcol[t] = M[t * LD + k];
+        __syncthreads();
+        if (t < nc)
+            M[k * LD + t] = t == k ? inv : M[k * LD + t] * inv;
+        __syncthreads();
+        if (ccol) {
+            const double rk = M[k * LD + cc];
+            for (int i = i0; i < nc; i += RP) {
+                if (i == k)
+                    continue;
+                if (cc == k)
+                    M[i * LD + cc] = -fcol[i] * inv;
+                else
+                    M[i * LD + cc] -= fcol[i] * rk;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int i = 0; i < nc; ++i)
+            rowidx[i] = i;
+        for (int k = 0; k < nc; ++k) {
+            const int tmp = rowidx[k];
+            rowidx[k] = rowidx[piv[k]];
+            rowidx[piv[k]] = tmp;
+        }
+    }
+    __syncthreads();
+    if (ccol)
+        for (int a = i0; a < nc; a += RP)
+            Minv[(int64_t)a * nc + rowidx[cc]] = (float)M[a * LD + cc];
+}
+
+// A (ml x nc, lda) <- [R; 0] with R upper triangular (nc x nc, ldr).
+__global__ void place_r_kernel(float *A, int64_t lda, int64_t ml, int nc, const float *R,
+                               int64_t ldr)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= ml * nc)
+        return;
+    const int64_t i = idx / nc;
+    const int j = (int)(idx % nc);
+    A[i * lda + j] = (i < nc && j >= i) ? R[i * ldr + j] : 0.0f;
+}
+
+// Q (m x n, ldq) <- [I_n; 0].
+__global__ void eye_kernel(float *Q, int64_t ldq, int64_t m, int64_t n)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= m * n)
+        return;
+    const int64_t i = idx / n, j = idx % n;
+    Q[i * ldq + j] = i == j ? 1.0f : 0.0f;
+}
+
+__global__ void clear_flag_kernel(int *flag) { flag[threadIdx.x] = 0; }
+
+// out (rows x cols, ldo) = sum over s of parts[s] (rows x cols, ld cols), in order.
+__global__ void sum_slices_kernel(const float *__restrict__ parts, int splits, int64_t rows,
+                                  int64_t cols, float *__restrict__ out, int64_t ldo)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= rows * cols)
+        return;
+    float acc = 0.0f;
+    for (int s = 0; s < splits; ++s)
+        acc += parts[(int64_t)s * rows * cols + idx];
+    out[(idx / cols) * ldo + idx % cols] = acc;
+}
+
+unsigned grid1d(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+// ----------------------------------------------------------------- planning
+
+size_t al(size_t b) { return align_up256(b); }
+
+// Levels of the TSQR tree for an m x nc panel: level 0 factors the rows of
+// A, level l >= 1 factors the stacked R factors of level l - 1
+// (rows[l] = nb[l - 1] * nc rows, held in buffer l of the workspace, which
+// then receives that level's Q in place).  The top level has one block.
+struct TsqrPlan {
+    int levels;                 // index of the top level
+    int64_t rows[kMaxLevels];
+    int nb[kMaxLevels];
+    size_t off[kMaxLevels];     // byte offset of buffer l (l >= 1)
+    size_t bytes;
+};
+
+TsqrPlan tsqr_plan(int64_t m, int nc)
+{
+    TsqrPlan p;
+    memset(&p, 0, sizeof p);
+    p.rows[0] = m;
+    p.nb[0] = make_part(m, nc).nb;
+    int l = 0;
+    size_t b = 0;
+    while (p.nb[l] > 1 && l + 1 < kMaxLevels) {
+        ++l;
+        p.rows[l] = (int64_t)p.nb[l - 1] * nc;
+        p.nb[l] = make_part(p.rows[l], nc).nb;
+        p.off[l] = b;
+        b += al((size_t)p.rows[l] * nc * sizeof(float));
+    }
+    p.levels = l;
+    p.bytes = b;
+    return p;
+}
+
+template <int B>
+hipError_t tsqr_run_b(const float *A, int64_t lda, int nc, float *Q, int64_t ldq, float *R,
+                      int64_t ldr, char *ws, const TsqrPlan &tp, hipStream_t s)
+{
+    const int L = tp.levels;
+    auto buf = [&](int l) { return (float *)(ws + tp.off[l]); };
+    for (int l = 0; l <= L; ++l) {
+        const Part pl = make_part(tp.rows[l], nc);
+        const float *in = l == 0 ? A : buf(l);
+        const int64_t ldi = l == 0 ? lda : nc;
+        float *qo = l == 0 ? Q : buf(l);
+        const int64_t ldo = l == 0 ? ldq : nc;
+        float *ro = l == L ? R : buf(l + 1);
+        const int64_t ldro = l == L ? ldr : nc;
+        hipLaunchKernelGGL(qr_block_kernel<B>, dim3(pl.nb), dim3(kQrThreads), 0, s, in, ldi, pl,
+                           nc, qo, ldo, ro, ldro);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const Part pl = make_part(tp.rows[l], nc);
+        float *io = l == 0 ? Q : buf(l);
+        const int64_t ld = l == 0 ? ldq : nc;
+        hipLaunchKernelGGL(rowmul_kernel<B>, dim3(pl.nb, kRows / 32), dim3(256), 0, s,
+                           (const float *)io, ld, pl, 0, nc, (const float *)buf(l + 1), io, ld,
+                           (float *)nullptr, (int64_t)0, 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t tsqr_run(const float *A, int64_t lda, int nc, float *Q, int64_t ldq, float *R,
+                    int64_t ldr, char *ws, const TsqrPlan &tp, hipStream_t s)
+{
+    if (nc <= 64)
+        return tsqr_run_b<64>(A, lda, nc, Q, ldq, R, ldr, ws, tp, s);
+    return tsqr_run_b<128>(A, lda, nc, Q, ldq, R, ldr, ws, tp, s);
+}
+
+// W = Q - [I; 0], Y = W (I - Q_1)^-1 for an m x nc Q; Minv: nc x nc scratch.
+template <int B>
+hipError_t wy_run_b(int64_t m, int nc, const float *Q, int64_t ldq, float *W, int64_t ldw,
+                    float *Y, int64_t ldy, float *Minv, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(wy_inverse_kernel<B>, dim3(1), dim3(512), 0, s, Q, ldq, nc, Minv, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const Part p = make_part(m, nc);
+    hipLaunchKernelGGL(rowmul_kernel<B>, dim3(p.nb, kRows / 32), dim3(256), 0, s, Q, ldq, p, 1,
+                       nc, (const float *)Minv, Y, ldy, W, ldw, 1);
+    return hipGetLastError();
+}
+
+hipError_t wy_run(int64_t m, int nc, const float *Q, int64_t ldq, float *W, int64_t ldw, float *Y,
+                  int64_t ldy, float *Minv, int *flag, hipStream_t s)
+{
+    if (nc <= 64)
+        return wy_run_b<64>(m, nc, Q, ldq, W, ldw, Y, ldy, Minv, flag, s);
+    return wy_run_b<128>(m, nc, Q, ldq, W, ldw, Y, ldy, Minv, flag, s);
+}
+
+size_t wy_bytes(int nc) { return al((size_t)nc * nc * sizeof(float)) + 256; }
+
+// Split count for a GEMM whose output (rows x cols) is small beside its K:
+// enough slices to give every compute unit about two tiles, each slice at
+// least 1024 deep.
+int splits_for(int prec, int64_t rows, int64_t cols, int64_t K, int num_cus)
+{
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.M = rows;
+    d.N = cols;
+    d.K = K;
+    d.lda = K;
+    d.ldb = cols;
+    d.ldc = cols;
+    d.a_kcontig = 0;
+    d.b_kcontig = 0;
+    gemm_finalize(d, prec);
+    const int64_t tiles = std::max<int64_t>(1, (int64_t)d.tiles_m * d.tiles_n);
+    int64_t sp = (2 * num_cus + tiles - 1) / tiles;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 1024));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, kMaxSplits));
+}
+
+// Split-K GEMMs Z (rows x cols, ld cols) = X^T V with X (K x rows, ldx) and
+// V (K x cols, ldv): the slices are independent problems of one grouped
+// persistent launch (so they run side by side), each writing its own slice
+// of parts (kMaxSplits x rows x cols scratch), summed in slice order.  The
+// descriptors of every such product of a factorisation are built on the host
+// first and uploaded once.
+struct SplitGemm {
+    int first_prob, first_item, num_items, splits, small;
+    float *Z, *parts;
+    int64_t rows, cols;
+};
+
+struct SplitBatch {
+    std::vector<GemmDesc> probs;
+    std::vector<GroupItem> items;
+    std::vector<SplitGemm> gemms;
+};
+
+void add_split(SplitBatch &sb, int prec, const float *X, int64_t ldx, const float *V, int64_t ldv,
+               int64_t rows, int64_t cols, int64_t K, float *Z, float *parts, int num_cus)
+{
+    const int splits = splits_for(prec, rows, cols, K, num_cus);
+    const int64_t ks = (K + splits - 1) / splits;
+    SplitGemm g;
+    g.first_prob = (int)sb.probs.size();
+    g.first_item = (int)sb.items.size();
+    g.splits = splits;
+    g.Z = Z;
+    g.parts = parts;
+    g.rows = rows;
+    g.cols = cols;
+    g.small = 0;
+    for (int sp = 0; sp < splits; ++sp) {
+        const int64_t k0 = sp * ks;
+        const int64_t kl = std::min<int64_t>(ks, K - k0);
+        GemmDesc d;
+        memset(&d, 0, sizeof d);
+        d.A = X + k0 * ldx;
+        d.lda = ldx;
+        d.a_kcontig = 0;
+        d.B = V + k0 * ldv;
+        d.ldb = ldv;
+        d.b_kcontig = 0;
+        d.C = splits == 1 ? Z : parts + (size_t)sp * rows * cols;
+        d.ldc = cols;
+        d.M = rows;
+        d.N = cols;
+        d.K = kl > 0 ? kl : 0;
+        d.alpha = 1.0f;
+        gemm_finalize(d, prec);
+        g.small = d.small;   // the same for every slice (it depends on M and N only)
+        const int pid = (int)sb.probs.size() - g.first_prob;
+        sb.probs.push_back(d);
+        for (int tt = 0; tt < d.num_tiles; ++tt)
+            sb.items.push_back(GroupItem{pid, tt});
+    }
+    g.num_items = (int)sb.items.size() - g.first_item;
+    sb.gemms.push_back(g);
+}
+
+// Upper bound of the items one split product of `cols` output columns adds
+// (rows <= 128, so one tile row): splits * tiles <= 2 num_cus + tiles, and
+// at most kMaxSplits * tiles; num_cus is taken as at most 1024.
+size_t split_items_bound(int64_t cols)
+{
+    const size_t tiles = (size_t)((cols + 127) / 128);
+    return std::min<size_t>(kMaxSplits * tiles, 2048 + tiles);
+}
+
+hipError_t run_split(int prec, const SplitBatch &sb, int which, const GemmDesc *probs_dev,
+                     const GroupItem *items_dev, int num_cus, hipStream_t s)
+{
+    const SplitGemm &g = sb.gemms[which];
+    hipError_t e = launch_gemm_grouped(prec, 0, 0, g.small, probs_dev + g.first_prob,
+                                       items_dev + g.first_item, g.num_items, num_cus, s);
+    if (e != hipSuccess || g.splits == 1)
+        return e;
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(grid1d(g.rows * g.cols)), dim3(256), 0, s,
+                       (const float *)g.parts, g.splits, g.rows, g.cols, g.Z, g.cols);
+    return hipGetLastError();
+}
+
+// C (rows x cols, ldc) -= X Z with X (rows x K, ldx) and Z (K x cols, ld cols).
+hipError_t gemm_sub(int prec, const float *X, int64_t ldx, const float *Z, int64_t rows,
+                    int64_t cols, int64_t K, float *C, int64_t ldc, hipStream_t s)
+{
+    GemmDesc d;
+    memset(&d, 0, sizeof d);
+    d.A = X;
+    d.lda = ldx;
+    d.a_kcontig = 1;
+    d.B = Z;
+    d.ldb = cols;
+    d.b_kcontig = 0;
+    d.C = C;
+    d.ldc = ldc;
+    d.E = C;
+    d.lde = ldc;
+    d.beta = 1.0f;
+    d.alpha = -1.0f;
+    d.M = rows;
+    d.N = cols;
+    d.K = K;
+    gemm_finalize(d, prec);
+    return launch_gemm(prec, d, s);
+}
+
+// Workspace of la_caqr, in order: Qr (m x b), Rr (b x b), the TSQR tree of an
+// m x b panel, Minv + flag, W and Y (m x n each with Q, m x b each without),
+// Z (b x n), split-K parts (kMaxSplits x b x n), split-K descriptors.
+struct CaqrWs {
+    size_t qr, rr, tree, wy, w, y, z, parts, probs, items, bytes;
+};
+
+CaqrWs caqr_ws(int64_t m, int64_t n, int b, int want_q)
+{
+    CaqrWs w;
+    size_t o = 0;
+    w.qr = o;
+    o += al((size_t)m * b * sizeof(float));
+    w.rr = o;
+    o += al((size_t)b * b * sizeof(float));
+    w.tree = o;
+    o += tsqr_plan(m, b).bytes;
+    w.wy = o;
+    o += wy_bytes(b);
+    const size_t wyb = al((size_t)m * (want_q ? n : b) * sizeof(float));
+    w.w = o;
+    o += wyb;
+    w.y = o;
+    o += wyb;
+    w.z = o;
+    o += al((size_t)b * n * sizeof(float));
+    w.parts = o;
+    o += al((size_t)kMaxSplits * b * n * sizeof(float));
+    // split-K descriptors of every panel (and of the Q pass)
+    const int64_t np = (n + b - 1) / b;
+    const size_t nprod = (size_t)np * (want_q ? 2 : 1);
+    w.probs = o;
+    o += al(nprod * kMaxSplits * sizeof(GemmDesc));
+    w.items = o;
+    o += al(nprod * split_items_bound(n) * sizeof(GroupItem));
+    w.bytes = o;
+    return w;
+}
+
+la_status read_flag(const int *flag, hipStream_t s, const char *who)
+{
+    int h = 0;
+    LA_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, s), who);
+    LA_HIP(hipStreamSynchronize(s), who);
+    if (h) {
+        set_error("%s: I - Q_1 is singular or nearly so (a pivot below 2^-16): the WY form of "
+                  "eq. (Yamamoto) breaks down", who);
+        return LA_ERR_BREAKDOWN;
+    }
+    return LA_OK;
+}
+
+la_status check_ws(void *ws, size_t ws_bytes, size_t need, const char *who)
+{
+    if (need > 0 && !ws) {
+        set_error("%s: NULL workspace", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (((uintptr_t)ws & 255u) != 0) {
+        set_error("%s: workspace must be 256-byte aligned", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (ws_bytes < need) {
+        set_error("%s: workspace %zu bytes, need %zu", who, ws_bytes, need);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    return LA_OK;
+}
+
+}  // namespace
+}  // namespace la
+
+using namespace la;
+
+extern "C" {
+
+size_t la_tsqr_workspace_size(int64_t m, int64_t n)
+{
+    if (n < 1 || n > kMaxPanel || m < n)
+        return 0;
+    return std::max<size_t>(256, tsqr_plan(m, (int)n).bytes);
+}
+
+la_status la_tsqr(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda, float *Q,
+                  int64_t ldq, float *R, int64_t ldr, void *workspace, size_t ws_bytes,
+                  void *hip_stream)
+{
+    static const char *who = "la_tsqr";
+    set_error("%s", "");
+    if (n < 1 || n > kMaxPanel || m < n || lda < n || ldq < n || ldr < n) {
+        set_error("%s: bad shape (m %lld, n %lld (1..128, <= m), lda %lld, ldq %lld, ldr %lld)",
+                  who, (long long)m, (long long)n, (long long)lda, (long long)ldq,
+                  (long long)ldr);
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx || !A || !Q || !R) {
+        set_error("%s: NULL argument", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    const TsqrPlan tp = tsqr_plan(m, (int)n);
+    la_status st = check_ws(workspace, ws_bytes, tp.bytes, who);
+    if (st != LA_OK)
+        return st;
+    const size_t qb = extent_bytes(m, n, ldq), rb = extent_bytes(n, n, ldr);
+    if (overlaps(Q, qb, A, extent_bytes(m, n, lda)) || overlaps(R, rb, A, extent_bytes(m, n, lda)) ||
+        overlaps(Q, qb, R, rb) || overlaps(Q, qb, workspace, tp.bytes) ||
+        overlaps(R, rb, workspace, tp.bytes)) {
+        set_error("%s: A, Q, R and the workspace must not overlap", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_tsqr: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    LA_HIP(tsqr_run(A, lda, (int)n, Q, ldq, R, ldr, (char *)workspace, tp, s), "la_tsqr: launch");
+    LA_HIP(hipStreamSynchronize(s), "la_tsqr: sync");
+    return LA_OK;
+}
+
+size_t la_wy_workspace_size(int64_t n)
+{
+    if (n < 1 || n > kMaxPanel)
+        return 0;
+    return wy_bytes((int)n);
+}
+
+la_status la_wy(la_context *ctx, int64_t m, int64_t n, const float *Q, int64_t ldq, float *W,
+                int64_t ldw, float *Y, int64_t ldy, void *workspace, size_t ws_bytes,
+                void *hip_stream)
+{
+    static const char *who = "la_wy";
+    set_error("%s", "");
+    if (n < 1 || n > kMaxPanel || m < n || ldq < n || ldw < n || ldy < n) {
+        set_error("%s: bad shape (m %lld, n %lld (1..128, <= m), ldq %lld, ldw %lld, ldy %lld)",
+                  who, (long long)m, (long long)n, (long long)ldq, (long long)ldw,
+                  (long long)ldy);
+        return LA_ERR_SHAPE;
+    }
+    if (!ctx || !Q || !W || !Y) {
+        set_error("%s: NULL argument", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t need = wy_bytes((int)n);
+    la_status st = check_ws(workspace, ws_bytes, need, who);
+    if (st != LA_OK)
+        return st;
+    const size_t qb = extent_bytes(m, n, ldq), wb = extent_bytes(m, n, ldw),
+                 yb = extent_bytes(m, n, ldy);
+    if (overlaps(W, wb, Q, qb) || overlaps(Y, yb, Q, qb) || overlaps(W, wb, Y, yb) ||
+        overlaps(W, wb, workspace, need) || overlaps(Y, yb, workspace, need)) {
+        set_error("%s: Q, W, Y and the workspace must not overlap", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    LA_HIP(hipSetDevice(ctx->device), "la_wy: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    float *Minv = (float *)workspace;
+    int *flag = (int *)((char *)workspace + al((size_t)n * n * sizeof(float)));
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    LA_HIP(hipGetLastError(), "la_wy: clear");
+    LA_HIP(wy_run(m, (int)n, Q, ldq, W, ldw, Y, ldy, Minv, flag, s), "la_wy: launch");
+    return read_flag(flag, s, who);
+}
+
+size_t la_caqr_workspace_size(int64_t m, int64_t n, int panel, int want_q)
+{
+    if (n < 1 || m < n || panel < 1 || panel > kMaxPanel)
+        return 0;
+    return caqr_ws(m, n, (int)std::min<int64_t>(panel, n), want_q).bytes;
+}
+
+la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, float *Q,
+                  int64_t ldq, int panel, void *workspace, size_t ws_bytes, la_precision prec,
+                  void *hip_stream)
+{
+    static const char *who = "la_caqr";
+    set_error("%s", "");
+    if (n < 1 || m < n || lda < n || (Q && ldq < n) || panel < 1 || panel > kMaxPanel) {
+        set_error("%s: bad shape (m %lld, n %lld, lda %lld, ldq %lld, panel %d (1..128))", who,
+                  (long long)m, (long long)n, (long long)lda, (long long)ldq, panel);
+        return LA_ERR_SHAPE;
+    }
+    if (!valid_prec(prec)) {
+        set_error("%s: unknown precision %d", who, (int)prec);
+        return LA_ERR_INVALID_ARG;
+    }
+    if (!ctx || !A) {
+        set_error("%s: NULL argument", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    const int b = (int)std::min<int64_t>(panel, n);
+    const CaqrWs cw = caqr_ws(m, n, b, Q != nullptr);
+    la_status st = check_ws(workspace, ws_bytes, cw.bytes, who);
+    if (st != LA_OK)
+        return st;
+    const size_t ab = extent_bytes(m, n, lda);
+    if (overlaps(A, ab, workspace, cw.bytes) ||
+        (Q && (overlaps(Q, extent_bytes(m, n, ldq), A, ab) ||
+               overlaps(Q, extent_bytes(m, n, ldq), workspace, cw.bytes)))) {
+        set_error("%s: A, Q and the workspace must not overlap", who);
+        return LA_ERR_INVALID_ARG;
+    }
+    const int pr = resolve_prec(prec, PREC_BF16X6);
+    LA_HIP(hipSetDevice(ctx->device), "la_caqr: hipSetDevice");
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *ws = (char *)workspace;
+    float *Qr = (float *)(ws + cw.qr), *Rr = (float *)(ws + cw.rr);
+    float *Minv = (float *)(ws + cw.wy);
+    int *flag = (int *)(ws + cw.wy + al((size_t)b * b * sizeof(float)));
+    float *Wb = (float *)(ws + cw.w), *Yb = (float *)(ws + cw.y);
+    float *Z = (float *)(ws + cw.z), *parts = (float *)(ws + cw.parts);
+    const int64_t ldwy = Q ? n : b;
+
+    const int64_t np = (n + b - 1) / b;
+    // split-K descriptors: W^T A_r of every panel, then Y^T Q of the Q pass
+    SplitBatch sb;
+    for (int64_t jp = 0; jp < np; ++jp) {
+        const int64_t c = jp * b, ml = m - c;
+        const int nc = (int)std::min<int64_t>(b, n - c);
+        const int64_t nr = n - c - nc;
+        const float *W = Q ? Wb + c * n + c : Wb;
+        if (nr > 0)
+            add_split(sb, pr, W, ldwy, A + c * lda + c + nc, lda, nc, nr, ml, Z, parts,
+                      ctx->num_cus);
+    }
+    const int nz = (int)sb.gemms.size();
+    if (Q)
+        for (int64_t jp = np - 1; jp >= 0; --jp) {
+            const int64_t c = jp * b, ml = m - c;
+            const int nc = (int)std::min<int64_t>(b, n - c);
+            add_split(sb, pr, Yb + c * n + c, n, Q + c * ldq + c, ldq, nc, n - c, ml, Z, parts,
+                      ctx->num_cus);
+        }
+    if (sb.probs.size() * sizeof(GemmDesc) > cw.items - cw.probs ||
+        sb.items.size() * sizeof(GroupItem) > cw.bytes - cw.items) {
+        set_error("%s: split-K descriptors exceed their workspace region", who);
+        return LA_ERR_OUT_OF_MEMORY;
+    }
+    GemmDesc *probs_dev = (GemmDesc *)(ws + cw.probs);
+    GroupItem *items_dev = (GroupItem *)(ws + cw.items);
+    if (!sb.probs.empty()) {
+        LA_HIP(hipMemcpyAsync(probs_dev, sb.probs.data(), sb.probs.size() * sizeof(GemmDesc),
+                              hipMemcpyHostToDevice, s),
+               "la_caqr: descriptors");
+        LA_HIP(hipMemcpyAsync(items_dev, sb.items.data(), sb.items.size() * sizeof(GroupItem),
+                              hipMemcpyHostToDevice, s),
+               "la_caqr: items");
+    }
+
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    LA_HIP(hipGetLastError(), "la_caqr: clear");
+    int zi = 0;
+    for (int64_t jp = 0; jp < np; ++jp) {
+        const int64_t c = jp * b, ml = m - c;
+        const int nc = (int)std::min<int64_t>(b, n - c);
+        const int64_t nr = n - c - nc;
+        float *Ap = A + c * lda + c;
+        float *W = Q ? Wb + c * n + c : Wb;
+        float *Y = Q ? Yb + c * n + c : Yb;
+        const TsqrPlan tp = tsqr_plan(ml, nc);
+        LA_HIP(tsqr_run(Ap, lda, nc, Qr, b, Rr, b, ws + cw.tree, tp, s), "la_caqr: tsqr");
+        LA_HIP(wy_run(ml, nc, Qr, b, W, ldwy, Y, ldwy, Minv, flag, s), "la_caqr: wy");
+        hipLaunchKernelGGL(place_r_kernel, dim3(grid1d(ml * nc)), dim3(256), 0, s, Ap, lda, ml,
+                           nc, (const float *)Rr, (int64_t)b);
+        LA_HIP(hipGetLastError(), "la_caqr: place R");
+        if (nr > 0) {
+            // A_r <- Q_f^T A_r = A_r - Y (W^T A_r)
+            LA_HIP(run_split(pr, sb, zi++, probs_dev, items_dev, ctx->num_cus, s),
+                   "la_caqr: W^T A_r");
+            LA_HIP(gemm_sub(pr, Y, ldwy, Z, ml, nr, nc, Ap + nc, lda, s), "la_caqr: update");
+        }
+    }
+    if (Q) {
+        hipLaunchKernelGGL(eye_kernel, dim3(grid1d(m * n)), dim3(256), 0, s, Q, ldq, m, n);
+        LA_HIP(hipGetLastError(), "la_caqr: eye");
+        int qi = nz;
+        for (int64_t jp = np - 1; jp >= 0; --jp) {
+            const int64_t c = jp * b, ml = m - c;
+            const int nc = (int)std::min<int64_t>(b, n - c);
+            const int64_t cols = n - c;
+            float *Qc = Q + c * ldq + c;
+            // Q[c:, c:] <- Q_f Q[c:, c:] = Q[c:, c:] - W (Y^T Q[c:, c:])
+            LA_HIP(run_split(pr, sb, qi++, probs_dev, items_dev, ctx->num_cus, s),
+                   "la_caqr: Y^T Q");
+            LA_HIP(gemm_sub(pr, Wb + c * n + c, n, Z, ml, cols, nc, Qc, ldq, s), "la_caqr: Q");
+        }
+    }
+    return read_flag(flag, s, who);
+}
+
+}  // extern "C"

@@ -26,7 +26,8 @@ def test_header_declares_expected_api():
     names = declared_functions()
     for n in ("la_create", "la_destroy", "la_gemm", "la_polar", "la_polar_workspace_size",
               "la_inverse", "la_inverse_workspace_size", "la_matfunc_odd", "la_matfunc_cheb",
-              "la_matfunc_workspace_size", "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
+              "la_matfunc_workspace_size", "la_tsqr", "la_tsqr_workspace_size", "la_wy",
+              "la_wy_workspace_size", "la_caqr", "la_caqr_workspace_size", "la_serve_create", "la_serve_submit", "la_serve_poll", "la_serve_destroy",
               "la_status_string", "la_last_error"):
         assert n in names
 
@@ -116,6 +117,34 @@ def test_matfunc_argument_validation_without_device(L):
                              None) == 1
     assert L.la_matfunc_cheb(None, 4, None, 2, 0.0, 1.0, cp, 2, None, 4, None, 0, 0, None) == 2
     assert L.la_matfunc_cheb(None, 4, None, 4, 0.0, 1.0, cp, 2, None, 4, None, 0, 0, None) == 1
+
+
+def test_qr_argument_validation_without_device(L):
+    # workspace sizes: 0 for rejected shapes
+    assert L.la_tsqr_workspace_size(100, 0) == 0
+    assert L.la_tsqr_workspace_size(100, 129) == 0
+    assert L.la_tsqr_workspace_size(10, 20) == 0
+    assert L.la_tsqr_workspace_size(256, 64) > 0          # one block: no tree buffers
+    # 70000 x 32: 274 blocks, then 8768, 1120 and 160 stacked rows
+    assert L.la_tsqr_workspace_size(70000, 32) >= 4 * 32 * (8768 + 1120 + 160)
+    assert L.la_wy_workspace_size(0) == 0 and L.la_wy_workspace_size(64) >= 64 * 64 * 4
+    assert L.la_caqr_workspace_size(100, 200, 64, 1) == 0
+    assert L.la_caqr_workspace_size(100, 100, 0, 1) == 0
+    assert L.la_caqr_workspace_size(100, 100, 129, 1) == 0
+    with_q = L.la_caqr_workspace_size(1000, 512, 64, 1)
+    assert with_q >= 2 * 4 * 1000 * 512 > L.la_caqr_workspace_size(1000, 512, 64, 0)
+    # shape errors come before any device work
+    assert L.la_tsqr(None, 10, 20, None, 20, None, 20, None, 20, None, 0, None) == 2
+    assert L.la_tsqr(None, 300, 129, None, 129, None, 129, None, 129, None, 0, None) == 2
+    assert L.la_tsqr(None, 300, 64, None, 63, None, 64, None, 64, None, 0, None) == 2
+    assert L.la_tsqr(None, 300, 64, None, 64, None, 64, None, 64, None, 0, None) == 1
+    assert L.la_wy(None, 300, 0, None, 64, None, 64, None, 64, None, 0, None) == 2
+    assert L.la_wy(None, 300, 64, None, 64, None, 64, None, 64, None, 0, None) == 1
+    assert L.la_caqr(None, 100, 200, None, 200, None, 200, 64, None, 0, 0, None) == 2
+    assert L.la_caqr(None, 300, 200, None, 200, None, 200, 129, None, 0, 0, None) == 2
+    assert L.la_caqr(None, 300, 200, None, 200, None, 200, 64, None, 0, 9, None) == 1
+    assert L.la_caqr(None, 300, 200, None, 200, None, 200, 64, None, 0, 0, None) == 1
+    assert L.la_last_error() == b"la_caqr: NULL argument"
 
 
 def test_create_reports_missing_device(L):
