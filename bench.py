@@ -244,6 +244,50 @@ def matfunc_section(la, torch, n=8192, degree=16, seed=701):
     return out
 
 
+def qr_section(la, torch, n=8192, panel=64, tall=(131072, 64), seed=801):
+    """Algorithm caqr on an n x n Gaussian A (R alone, then R and Q) at AUTO
+    (6xBF16 updates) and all-FP32 MFMA, and Algorithm tsqr of a tall panel.
+    Rates use the Householder operation counts: 4/3 n^3 for R, as much again
+    for Q; 2 m k^2 - 2/3 k^3 for R and as much for Q of an m x k panel."""
+    g = torch.Generator(device="cuda:0").manual_seed(seed)
+    A = torch.randn((n, n), device="cuda:0", generator=g)
+    X = torch.empty_like(A)
+    out = {"workload": f"CAQR of a {n}x{n} Gaussian A (seed {seed}), panel {panel}; TSQR of a "
+                       f"{tall[0]}x{tall[1]} Gaussian panel"}
+    for name, prec in (("auto", la.Precision.AUTO), ("fp32", la.Precision.FP32)):
+        res = {}
+        for want_q in (False, True):
+            ws = torch.empty(la.caqr_workspace_size(n, n, panel, want_q) + 256,
+                             dtype=torch.uint8, device="cuda:0")
+            def run():
+                X.copy_(A)
+                la.caqr(X, panel=panel, want_q=want_q, inplace=True, prec=prec, workspace=ws)
+            run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            flops = 4.0 / 3.0 * float(n) ** 3 * (2.0 if want_q else 1.0)
+            res["r_and_q" if want_q else "r_only"] = {
+                "seconds": round(dt, 4), "tflops_algorithmic": round(flops / dt / 1e12, 2)}
+            del ws
+        out[name] = res
+        print(f"[bench] caqr {name}: {res}", file=sys.stderr, flush=True)
+    m, k = tall
+    T = torch.randn((m, k), device="cuda:0", generator=g)
+    la.tsqr(T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    la.tsqr(T)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    flops = 2.0 * (2.0 * m * k * k - 2.0 / 3.0 * k ** 3)
+    out["tsqr"] = {"seconds": round(dt, 5), "tflops_algorithmic": round(flops / dt / 1e12, 2)}
+    print(f"[bench] tsqr {m}x{k}: {out['tsqr']}", file=sys.stderr, flush=True)
+    return out
+
+
 def serving_pool(torch, pool_size=48, seed=401):
     """Pool of square polar inputs (n log-uniform in [128, 4096], cond 10^U(1,6))."""
     import la_inputs
@@ -357,6 +401,9 @@ def main():
     ap.add_argument("--no-oracle-polar", action="store_true")
     ap.add_argument("--no-inverse", action="store_true")
     ap.add_argument("--no-matfunc", action="store_true")
+    ap.add_argument("--no-qr", action="store_true")
+    ap.add_argument("--qr-only", action="store_true",
+                    help="run only the QR section (for profiling its kernels)")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -383,6 +430,9 @@ def main():
     import la_inputs
     import paper_2112_09017_amd as la
 
+    if args.qr_only:
+        print(json.dumps({"qr": qr_section(la, torch)}), flush=True)
+        return
     if args.serving_only:
         pool = serving_pool(torch)
         print(json.dumps({"serving": serving_section(la, pool, duration=args.serving_seconds)}),
@@ -506,6 +556,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_matfunc and args.only is None:
         out["matfunc"] = matfunc_section(la, torch)
+    if not args.no_qr and args.only is None:
+        out["qr"] = qr_section(la, torch)
         torch.cuda.empty_cache()
     if not args.no_serving and args.only is None:
         pool = serving_pool(torch)
