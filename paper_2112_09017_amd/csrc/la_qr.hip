@@ -34,7 +34,6 @@ namespace la {
 namespace {
 
 constexpr int kRows = 256;        // rows of one local factorisation
-constexpr int kQrThreads = 512;
 constexpr int kMaxPanel = 128;
 constexpr int kMaxLevels = 40;
 constexpr int kMaxSplits = 16;
@@ -76,80 +75,98 @@ __host__ __device__ inline int64_t part_block(const Part &p, int64_t r)
 
 // ---------------------------------------------------------------- kernels
 
-// Householder QR of one row block (rows x nc, rows <= 256, nc <= B) per
-// workgroup, with the block resident in registers: thread (c, g) holds
-// column c over the RPG rows of group g.  Reflection j uses u = x - beta e_j
-// (x = column j from row j down, beta = -sign(x_j) ||x||) unscaled, and
-// H_j = I - kappa u u^T with kappa = 1 / (beta (beta - x_j)); column j keeps
-// x below the diagonal, u_j and kappa go to LDS arrays.  The owners of the
-// next column publish it to LDS (ubuf) after each update, with FP64 partial
-// sums of its squares below the diagonal (four FP32 squares at a time), so
-// every step is: norm and reflection from the published column, partial dot
-// products u^T x_c per group, one barrier, the rank-1 update, one barrier.
-// Row chunks above the diagonal are skipped.  R (row block blk of R, ld ldr)
-// is written from the registers; then Q = H_0 ... H_{nc-1} [I; 0] is formed
-// in place, last reflection first (column j becomes H_j e_j once the columns
-// to its right hold H_{j+1} ... e_c), and written to Q (ldq).  X may equal Q.
-template <int B>
-__global__ __launch_bounds__(kQrThreads) void qr_block_kernel(const float *X, int64_t ldx,
-                                                              Part part, int nc, float *Q,
-                                                              int64_t ldq, float *R, int64_t ldr)
+// Sum over the L consecutive lanes of an aligned lane group (L = 4 or 8),
+// returned in every lane of the group, by DPP moves within the group
+// (lane ^ 1, lane ^ 2, then the mirror of each half-row of 8).
+template <int CTRL>
+__device__ inline float dpp_f32(float v)
 {
-    constexpr int G = kQrThreads / B;
-    constexpr int RPG = kRows / G;
-    constexpr int PD = G + 4;   // row stride of pdot (16-byte multiple)
-    static_assert(RPG % 4 == 0 && G % 4 == 0, "groups are handled four rows at a time");
-    static_assert(B % 64 == 0, "a wave must not straddle two row groups");
-    __shared__ __attribute__((aligned(16))) float ubuf[kRows];
-    __shared__ __attribute__((aligned(16))) float pdot[B * PD];
-    __shared__ double psq[G];
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int L, typename T>
+__device__ inline T group_sum(T v)
+{
+    static_assert(L == 4 || L == 8, "lane groups of 4 or 8");
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f32<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+        v += dpp_f32<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+        if constexpr (L == 8)
+            v += dpp_f32<0x141>(v);   // row_half_mirror
+    } else {
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        if constexpr (L == 8)
+            v += dpp_f64<0x141>(v);
+    }
+    return v;
+}
+
+// Householder QR of one row block (rows x nc, rows <= 256, nc <= B) per
+// workgroup of 8 B threads, the block in registers.  Wave w owns columns
+// 8 w .. 8 w + 7; within the wave a column is held by L = 8 consecutive
+// lanes, each with RPL = 32 consecutive rows, so the column dot products
+// reduce inside the wave (group_sum) without a barrier.
+//
+// Reflection j uses u = x - beta e_j (x = column j from row j down,
+// beta = -sign(x_j) ||x||, norm in FP64) unscaled, H_j = I - kappa u u^T,
+// kappa = 1 / (beta (beta - x_j)).  The owners of column j form u (zero above
+// row j, u_j = x_j - beta below it x) and publish it to one of two LDS
+// buffers with kappa; after one barrier every column c > j forms u^T x_c and
+// x_c -= kappa (u^T x_c) u, and the owners of column j + 1 (already updated)
+// prepare the next reflection into the other buffer.  One barrier per step.
+// Column j keeps x below the diagonal and the pivot x_j on it; u_j, kappa and
+// beta go to LDS arrays.  R (row block blk of R, ld ldr) is then written from
+// the registers, and Q = H_0 ... H_{nc-1} [I; 0] is formed in place, last
+// reflection first (column j becomes H_j e_j once the columns to its right
+// hold H_{j+1} ... e_c), and written to Q (ldq).  X may equal Q.
+template <int B>
+__global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t ldx, Part part,
+                                                         int nc, float *Q, int64_t ldq, float *R,
+                                                         int64_t ldr)
+{
+    constexpr int CPW = 8;              // columns per wave
+    constexpr int L = 64 / CPW;         // lanes per column
+    constexpr int RPL = kRows / L;      // rows per lane
+    __shared__ __attribute__((aligned(16))) float ubuf[2][kRows];
     __shared__ float s_u0[B], s_kap[B], s_beta[B];
 
-    const int t = threadIdx.x;
-    // B >= 64: every wave lies in one row group, so g (and the row-chunk
-    // tests below) are wave-uniform
-    const int c = t % B, g = __builtin_amdgcn_readfirstlane(t / B);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int c = w * CPW + lane / L;
+    const int rlo = (lane % L) * RPL;
     const int64_t blk = blockIdx.x;
     const int64_t r0 = part_start(part, blk);
     const int rows = (int)(part_start(part, blk + 1) - r0);
-    const int rlo = g * RPG;
     nc = __builtin_amdgcn_readfirstlane(nc);
     const bool col = c < nc;
 
-    float f[RPG], u[RPG];
+    float f[RPL], u[RPL];
 #pragma unroll
-    for (int i = 0; i < RPG; ++i)
+    for (int i = 0; i < RPL; ++i)
         f[i] = (col && rlo + i < rows) ? X[(r0 + rlo + i) * ldx + c] : 0.0f;
 
-    // column of this thread -> ubuf; FP64 partial sum of squares of rows > lim
-    auto publish = [&](int lim) {
+    // owners of column jn (all L lanes): reflection jn from their column,
+    // published to ubuf[jn & 1] and the scalar arrays
+    auto prepare = [&](int jn) {
         double s = 0.0;
+        float x0p = 0.0f;
 #pragma unroll
-        for (int i = 0; i < RPG; i += 4) {
-            *(float4 *)&ubuf[rlo + i] = make_float4(f[i], f[i + 1], f[i + 2], f[i + 3]);
-            float q = 0.0f;
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (rlo + i + e > lim)
-                    q = fmaf(f[i + e], f[i + e], q);
-            s += (double)q;
+        for (int i = 0; i < RPL; ++i) {
+            const int r = rlo + i;
+            if (r > jn)
+                s = fma((double)f[i], (double)f[i], s);
+            if (r == jn)
+                x0p = f[i];
         }
-        psq[g] = s;
-    };
-
-    if (c == 0)
-        publish(0);
-    __syncthreads();
-
-    for (int jv = 0; jv < nc; ++jv) {
-        // the step index is the same in every lane: keep it (and every row
-        // chunk test derived from it) scalar
-        const int j = __builtin_amdgcn_readfirstlane(jv);
-        double sig = 0.0;
-        for (int q = 0; q < G; ++q)
-            sig += psq[q];
-        const double x0 = ubuf[j];
-        const double nrm = sqrt(x0 * x0 + sig);
+        s = group_sum<L>(s);
+        const double x0 = group_sum<L>(x0p);   // one lane holds it, the others add zero
+        const double nrm = sqrt(x0 * x0 + s);
         float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
         if (nrm > 0.0) {
             const double bt = x0 >= 0.0 ? -nrm : nrm;
@@ -157,144 +174,116 @@ __global__ __launch_bounds__(kQrThreads) void qr_block_kernel(const float *X, in
             kap = (float)(1.0 / (bt * (bt - x0)));
             beta = (float)bt;
         }
-        if (t == 0) {
-            s_u0[j] = u0;
-            s_kap[j] = kap;
-            s_beta[j] = beta;
+        if (rlo == 0) {
+            s_u0[jn] = u0;
+            s_kap[jn] = kap;
+            s_beta[jn] = beta;
         }
-        const bool act = col && c > j;
-        float d = 0.0f;
-        if (act) {
-            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float *ub = ubuf[jn & 1];
 #pragma unroll
-            for (int i = 0; i < RPG; i += 4) {
-                if (rlo + i > j) {
-                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
-                    u[i] = uv.x;
-                    u[i + 1] = uv.y;
-                    u[i + 2] = uv.z;
-                    u[i + 3] = uv.w;
+        for (int i = 0; i < RPL; i += 4) {
+            float o[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
-                } else if (rlo + i + 3 >= j) {
-                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
-                    const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = rlo + i + e;
-                        u[i + e] = r < j ? 0.0f : (r == j ? u0 : ua[e]);
-                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
-                    }
-                }
+            for (int e = 0; e < 4; ++e) {
+                const int r = rlo + i + e;
+                o[e] = r < jn ? 0.0f : (r == jn ? u0 : f[i + e]);
             }
-            d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+            *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
         }
-        pdot[c * PD + g] = d;
-        __syncthreads();
-        if (act) {
-            float w = 0.0f;
+    };
+    // owners of column jn: its stored reflector (x below the diagonal) to ubuf[jn & 1]
+    auto republish = [&](int jn) {
+        const float u0 = s_u0[jn];
+        float *ub = ubuf[jn & 1];
 #pragma unroll
-            for (int q = 0; q < G; q += 4) {
-                const float4 p = *(const float4 *)&pdot[c * PD + q];
-                w += p.x;
-                w += p.y;
-                w += p.z;
-                w += p.w;
+        for (int i = 0; i < RPL; i += 4) {
+            float o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = rlo + i + e;
+                o[e] = r < jn ? 0.0f : (r == jn ? u0 : f[i + e]);
             }
-            const float sc = kap * w;
-#pragma unroll
-            for (int i = 0; i < RPG; i += 4)
-                if (rlo + i + 3 >= j) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        f[i + e] = fmaf(-sc, u[i + e], f[i + e]);
-                }
-            if (c == j + 1)
-                publish(j + 1);
+            *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
         }
+    };
+
+    // f -= sc u with the u of the current step
+    auto axpy_u = [&](float sc) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            f[i] = fmaf(-sc, u[i], f[i]);
+    };
+
+    if (c == 0)
+        prepare(0);
+    __syncthreads();
+    for (int jv = 0; jv < nc; ++jv) {
+        const int j = __builtin_amdgcn_readfirstlane(jv);
+        const float *ub = ubuf[j & 1];
+        const float kap = s_kap[j];
+        float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < RPL; i += 4) {
+            const float4 uv = *(const float4 *)&ub[rlo + i];
+            const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                u[i + e] = ua[e];
+                d4[e] = fmaf(ua[e], f[i + e], d4[e]);
+            }
+        }
+        const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+        const float sc = (col && c > j) ? kap * d : 0.0f;
+        axpy_u(sc);
+        if (c == j + 1 && col)
+            prepare(j + 1);
         __syncthreads();
     }
 
     float *Rb = R + blk * nc * ldr;
 #pragma unroll
-    for (int i = 0; i < RPG; ++i) {
+    for (int i = 0; i < RPL; ++i) {
         const int rr = rlo + i;
         if (col && rr < nc)
             Rb[(int64_t)rr * ldr + c] = c > rr ? f[i] : (c == rr ? s_beta[rr] : 0.0f);
     }
 
     if (c == nc - 1)
-        publish(kRows);
+        republish(nc - 1);
     __syncthreads();
     for (int jv = nc - 1; jv >= 0; --jv) {
         const int j = __builtin_amdgcn_readfirstlane(jv);
-        const float u0 = s_u0[j], kap = s_kap[j];
-        const bool upd = col && c > j;
-        const bool form = c == j;
-        float d = 0.0f;
-        if (upd || form) {
-            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float *ub = ubuf[j & 1];
+        const float kap = s_kap[j], u0 = s_u0[j];
+        float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int i = 0; i < RPG; i += 4) {
-                if (rlo + i > j) {
-                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
-                    u[i] = uv.x;
-                    u[i + 1] = uv.y;
-                    u[i + 2] = uv.z;
-                    u[i + 3] = uv.w;
+        for (int i = 0; i < RPL; i += 4) {
+            const float4 uv = *(const float4 *)&ub[rlo + i];
+            const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
-                } else if (form || rlo + i + 3 >= j) {
-                    const float4 uv = *(const float4 *)&ubuf[rlo + i];
-                    const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int r = rlo + i + e;
-                        u[i + e] = r < j ? 0.0f : (r == j ? u0 : ua[e]);
-                        d4[e] = fmaf(u[i + e], f[i + e], d4[e]);
-                    }
-                }
+            for (int e = 0; e < 4; ++e) {
+                u[i + e] = ua[e];
+                d4[e] = fmaf(ua[e], f[i + e], d4[e]);
             }
-            d = (d4[0] + d4[1]) + (d4[2] + d4[3]);
         }
-        pdot[c * PD + g] = d;
-        __syncthreads();
-        if (upd) {
-            float w = 0.0f;
-#pragma unroll
-            for (int q = 0; q < G; q += 4) {
-                const float4 p = *(const float4 *)&pdot[c * PD + q];
-                w += p.x;
-                w += p.y;
-                w += p.z;
-                w += p.w;
-            }
-            const float sc = kap * w;
-#pragma unroll
-            for (int i = 0; i < RPG; i += 4)
-                if (rlo + i + 3 >= j) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        f[i + e] = fmaf(-sc, u[i + e], f[i + e]);
-                }
-        } else if (form) {
-            // column j = H_j e_j = e_j - kappa u_j u (zero above row j)
+        const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+        if (col && c > j) {
+            axpy_u(kap * d);
+        } else if (c == j) {
+            // column j = H_j e_j = e_j - kappa u_j u (u is zero above row j)
             const float s2 = kap * u0;
 #pragma unroll
-            for (int i = 0; i < RPG; ++i) {
-                const int r = rlo + i;
-                f[i] = r < j ? 0.0f : fmaf(-s2, u[i], r == j ? 1.0f : 0.0f);
-            }
+            for (int i = 0; i < RPL; ++i)
+                f[i] = rlo + i == j ? 1.0f : 0.0f;
+            axpy_u(s2);
         }
         if (c == j - 1)
-            publish(kRows);
+            republish(j - 1);
         __syncthreads();
     }
 
 #pragma unroll
-    for (int i = 0; i < RPG; ++i)
+    for (int i = 0; i < RPL; ++i)
         if (col && rlo + i < rows)
             Q[(r0 + rlo + i) * ldq + c] = f[i];
 }
@@ -543,8 +532,8 @@ hipError_t tsqr_run_b(const float *A, int64_t lda, int nc, float *Q, int64_t ldq
         const int64_t ldo = l == 0 ? ldq : nc;
         float *ro = l == L ? R : buf(l + 1);
         const int64_t ldro = l == L ? ldr : nc;
-        hipLaunchKernelGGL(qr_block_kernel<B>, dim3(pl.nb), dim3(kQrThreads), 0, s, in, ldi, pl,
-                           nc, qo, ldo, ro, ldro);
+        hipLaunchKernelGGL(qr_block_kernel<B>, dim3(pl.nb), dim3(8 * B), 0, s, in, ldi, pl, nc,
+                           qo, ldo, ro, ldro);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
