@@ -151,22 +151,26 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     for (int i = 0; i < RPL; ++i)
         f[i] = (col && rlo + i < rows) ? X[(r0 + rlo + i) * ldx + c] : 0.0f;
 
-    // owners of column jn (all L lanes): reflection jn from their column,
-    // published to ubuf[jn & 1] and the scalar arrays
+    // owners of column jn (all L lanes): reflection jn from their column.
+    // The column from row jn down (zero above) goes to ubuf[jn & 1] while
+    // ||x||^2 accumulates in FP64 (FP32 products are exact in FP64); the pivot
+    // x_jn is read back from LDS (one wave's LDS accesses complete in order),
+    // and its lane overwrites it with u_jn once beta is known.
     auto prepare = [&](int jn) {
+        float *ub = ubuf[jn & 1];
         double s = 0.0;
-        float x0p = 0.0f;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            const int r = rlo + i;
-            if (r > jn)
-                s = fma((double)f[i], (double)f[i], s);
-            if (r == jn)
-                x0p = f[i];
+        for (int i = 0; i < RPL; i += 4) {
+            float o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                o[e] = rlo + i + e < jn ? 0.0f : f[i + e];
+                s = fma((double)o[e], (double)o[e], s);
+            }
+            *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
         }
-        s = group_sum<L>(s);
-        const double x0 = group_sum<L>(x0p);   // one lane holds it, the others add zero
-        const double nrm = sqrt(x0 * x0 + s);
+        const double nrm = sqrt(group_sum<L>(s));
+        const double x0 = ub[jn];
         float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
         if (nrm > 0.0) {
             const double bt = x0 >= 0.0 ? -nrm : nrm;
@@ -179,17 +183,8 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             s_kap[jn] = kap;
             s_beta[jn] = beta;
         }
-        float *ub = ubuf[jn & 1];
-#pragma unroll
-        for (int i = 0; i < RPL; i += 4) {
-            float o[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int r = rlo + i + e;
-                o[e] = r < jn ? 0.0f : (r == jn ? u0 : f[i + e]);
-            }
-            *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
-        }
+        if (rlo <= jn && jn < rlo + RPL)
+            ub[jn] = u0;
     };
     // owners of column jn: its stored reflector (x below the diagonal) to ubuf[jn & 1]
     auto republish = [&](int jn) {
@@ -711,6 +706,14 @@ hipError_t gemm_sub(int prec, const float *X, int64_t ldx, const float *Z, int64
     d.N = cols;
     d.K = K;
     gemm_finalize(d, prec);
+    if (K <= 128 && !d.small) {
+        // K is the panel width: the launch streams C in and out, and the smaller
+        // tile class keeps more tiles in flight (the class never changes a result)
+        d.small = 1;
+        d.tiles_m = (int)((rows + tile_m(prec, 1) - 1) / tile_m(prec, 1));
+        d.tiles_n = (int)((cols + tile_n(prec, 1) - 1) / tile_n(prec, 1));
+        d.num_tiles = d.tiles_m * d.tiles_n;
+    }
     return launch_gemm(prec, d, s);
 }
 
