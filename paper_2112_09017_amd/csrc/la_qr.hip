@@ -348,94 +348,95 @@ __global__ __launch_bounds__(256) void rowmul_kernel(const float *in, int64_t ld
 }
 
 // Minv = (I - Q_1)^-1 for the top nc x nc block Q_1 of Q (ld ldq), by
-// Gauss-Jordan elimination with partial pivoting in FP64 in LDS; rounded to
-// FP32 (nc x nc, ld nc).  flag[0] = 1 if a pivot is below kPivotFloor in
-// magnitude or not finite.  The row interchanges are undone by writing
-// column i of the eliminated array to column rowidx[i] of the inverse.
+// Gauss-Jordan elimination with partial pivoting in FP64 in LDS (512
+// threads; thread (i0, c) owns column c of rows i0, i0 + 512 / B, ...).
+// Rows are not moved: step k pivots on the unused row p_k with the largest
+// |M[p_k][k]| (compared in FP32, ties to the lower row; every wave finds it
+// itself), scales row p_k and eliminates column k from the other rows, with
+// one barrier between reading the operands and writing the results and one
+// after.  The array then holds (P M)^-1 in pivot order, and
+// Minv[k][p_c] = B[p_k][c].  Rounded to FP32 (nc x nc, ld nc).  flag[0] = 1
+// if a pivot is below kPivotFloor in magnitude or not finite.
 template <int B>
 __global__ __launch_bounds__(512) void wy_inverse_kernel(const float *__restrict__ Q, int64_t ldq,
                                                          int nc, float *__restrict__ Minv,
                                                          int *flag)
 {
     constexpr int LD = B + 1;
-    constexpr int RP = 512 / B;   // rows handled at a time: thread (i0, cc) takes rows i0 + RP q
+    constexpr int RP = 512 / B;   // row phases: thread (i0, c) takes rows i0 + RP q
+    constexpr int RO = B / RP;    // rows owned per thread
+    constexpr int RL = B / 64;    // rows per lane in the pivot search
     __shared__ double M[B * LD];
-    __shared__ double fcol[B];
     __shared__ int piv[B];
-    __shared__ int rowidx[B];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     const int cc = t % B, i0 = t / B;
+    nc = __builtin_amdgcn_readfirstlane(nc);
     const bool ccol = cc < nc;
     for (int i = i0; i < nc; i += RP)
         if (ccol)
             M[i * LD + cc] = (i == cc ? 1.0 : 0.0) - (double)Q[(int64_t)i * ldq + cc];
+    bool used[RL];
+#pragma unroll
+    for (int q = 0; q < RL; ++q)
+        used[q] = false;
     __syncthreads();
-    for (int k = 0; k < nc; ++k) {
-        if (t < 64) {
-            double best = -1.0;
-            int bi = k;
-            for (int i = k + t; i < nc; i += 64) {
-                const double a = fabs(M[i * LD + k]);
-                if (a > best) {
-                    best = a;
-                    bi = i;
-                }
+    for (int kv = 0; kv < nc; ++kv) {
+        const int k = __builtin_amdgcn_readfirstlane(kv);
+        // pivot (every wave): key = FP32 magnitude bits (low 7 mantissa bits dropped) | (127 - row)
+        unsigned key = 0;
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            const int r = lane + 64 * q;
+            if (r < nc && !used[q]) {
+                const unsigned kk = ((unsigned)__float_as_int((float)fabs(M[r * LD + k])) & ~0x7Fu) |
+                                    (unsigned)(127 - r);
+                key = kk > key ? kk : key;
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if (t == 0)
-                piv[k] = bi;
         }
-        __syncthreads();
-        const int p = piv[k];
-        if (p != k && t < nc) {
-            const double tmp = M[k * LD + t];
-            M[k * LD + t] = M[p * LD + t];
-            M[p * LD + t] = tmp;
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned o = (unsigned)__shfl_xor((int)key, off);
+            key = o > key ? o : key;
         }
-        __syncthreads();
-        const double pv = M[k * LD + k];
+        const int p = __builtin_amdgcn_readfirstlane(127 - (int)(key & 0x7Fu));
+#pragma unroll
+        for (int q = 0; q < RL; ++q)
+            if (lane + 64 * q == p)
+                used[q] = true;
+        const double pv = M[p * LD + k];
         const double inv = 1.0 / pv;
-        if (t == 0 && !(fabs(pv) >= kPivotFloor && isfinite(pv)))
-            flag[0] = 1;
-        if (t < nc)
-            fcol[t] = M[t * LD + k];
-        __syncthreads();
-        if (t < nc)
-            M[k * LD + t] = t == k ? inv : M[k * LD + t] * inv;
+        const double prc = ccol ? M[p * LD + cc] : 0.0;
+        double mic[RO], fic[RO];
+#pragma unroll
+        for (int q = 0; q < RO; ++q) {
+            const int i = i0 + RP * q;
+            mic[q] = (i < nc && ccol) ? M[i * LD + cc] : 0.0;
+            fic[q] = i < nc ? M[i * LD + k] : 0.0;
+        }
+        if (t == 0) {
+            piv[k] = p;
+            if (!(fabs(pv) >= kPivotFloor && isfinite(pv)))
+                flag[0] = 1;
+        }
         __syncthreads();
         if (ccol) {
-            const double rk = M[k * LD + cc];
-            for (int i = i0; i < nc; i += RP) {
-                if (i == k)
+#pragma unroll
+            for (int q = 0; q < RO; ++q) {
+                const int i = i0 + RP * q;
+                if (i >= nc)
                     continue;
-                if (cc == k)
-                    M[i * LD + cc] = -fcol[i] * inv;
+                double v;
+                if (i == p)
+                    v = cc == k ? inv : prc * inv;
                 else
-                    M[i * LD + cc] -= fcol[i] * rk;
+                    v = cc == k ? -fic[q] * inv : fma(-fic[q] * inv, prc, mic[q]);
+                M[i * LD + cc] = v;
             }
         }
         __syncthreads();
     }
-    if (t == 0) {
-        for (int i = 0; i < nc; ++i)
-            rowidx[i] = i;
-        for (int k = 0; k < nc; ++k) {
-            const int tmp = rowidx[k];
-            rowidx[k] = rowidx[piv[k]];
-            rowidx[piv[k]] = tmp;
-        }
-    }
-    __syncthreads();
-    if (ccol)
-        for (int a = i0; a < nc; a += RP)
-            Minv[(int64_t)a * nc + rowidx[cc]] = (float)M[a * LD + cc];
+    for (int k = i0; k < nc; k += RP)
+        if (ccol)
+            Minv[(int64_t)k * nc + piv[cc]] = (float)M[piv[k] * LD + cc];
 }
 
 // A (ml x nc, lda) <- [R; 0] with R upper triangular (nc x nc, ldr).
