@@ -68,11 +68,6 @@ __host__ __device__ inline int64_t part_start(const Part &p, int64_t i)
     return i == p.nb - 1 ? p.last_start : kRows * i;
 }
 
-__host__ __device__ inline int64_t part_block(const Part &p, int64_t r)
-{
-    return r >= p.last_start ? p.nb - 1 : r / kRows;
-}
-
 // ---------------------------------------------------------------- kernels
 
 // Sum over the L consecutive lanes of an aligned lane group (L = 4 or 8),
@@ -719,10 +714,12 @@ hipError_t gemm_sub(int prec, const float *X, int64_t ldx, const float *Z, int64
 }
 
 // Workspace of la_caqr, in order: Qr (m x b), Rr (b x b), the TSQR tree of an
-// m x b panel, Minv + flag, W and Y (m x n each with Q, m x b each without),
-// Z (b x n), split-K parts (kMaxSplits x b x n), split-K descriptors.
+// m x b panel, Minv + flag, W and Y (m x n each with Q; without Q two m x b
+// buffers each, alternating between panels), then for the critical stream Z0
+// (b x b) and its split-K parts, for the trailing stream Z1 (b x n) and its
+// parts, and the split-K descriptors.
 struct CaqrWs {
-    size_t qr, rr, tree, wy, w, y, z, parts, probs, items, bytes;
+    size_t qr, rr, tree, wy, w, y, z0, parts0, z1, parts1, probs, items, bytes;
 };
 
 CaqrWs caqr_ws(int64_t m, int64_t n, int b, int want_q)
@@ -737,18 +734,23 @@ CaqrWs caqr_ws(int64_t m, int64_t n, int b, int want_q)
     o += tsqr_plan(m, b).bytes;
     w.wy = o;
     o += wy_bytes(b);
-    const size_t wyb = al((size_t)m * (want_q ? n : b) * sizeof(float));
+    const size_t wyb = al((size_t)m * (want_q ? n : 2 * b) * sizeof(float));
     w.w = o;
     o += wyb;
     w.y = o;
     o += wyb;
-    w.z = o;
+    w.z0 = o;
+    o += al((size_t)b * b * sizeof(float));
+    w.parts0 = o;
+    o += al((size_t)kMaxSplits * b * b * sizeof(float));
+    w.z1 = o;
     o += al((size_t)b * n * sizeof(float));
-    w.parts = o;
+    w.parts1 = o;
     o += al((size_t)kMaxSplits * b * n * sizeof(float));
-    // split-K descriptors of every panel (and of the Q pass)
+    // split-K descriptors: next-panel and trailing products of every panel,
+    // and the Q pass
     const int64_t np = (n + b - 1) / b;
-    const size_t nprod = (size_t)np * (want_q ? 2 : 1);
+    const size_t nprod = (size_t)np * (want_q ? 3 : 2);
     w.probs = o;
     o += al(nprod * kMaxSplits * sizeof(GemmDesc));
     w.items = o;
@@ -756,6 +758,21 @@ CaqrWs caqr_ws(int64_t m, int64_t n, int b, int want_q)
     w.bytes = o;
     return w;
 }
+
+// The second stream and the two events of one la_caqr call.
+struct LookAhead {
+    hipStream_t s1 = nullptr;
+    hipEvent_t wy_ready = nullptr, trail_done = nullptr;
+    ~LookAhead()
+    {
+        if (wy_ready)
+            (void)hipEventDestroy(wy_ready);
+        if (trail_done)
+            (void)hipEventDestroy(trail_done);
+        if (s1)
+            (void)hipStreamDestroy(s1);
+    }
+};
 
 la_status read_flag(const int *flag, hipStream_t s, const char *who)
 {
@@ -925,27 +942,42 @@ la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, 
     float *Minv = (float *)(ws + cw.wy);
     int *flag = (int *)(ws + cw.wy + al((size_t)b * b * sizeof(float)));
     float *Wb = (float *)(ws + cw.w), *Yb = (float *)(ws + cw.y);
-    float *Z = (float *)(ws + cw.z), *parts = (float *)(ws + cw.parts);
+    float *Z0 = (float *)(ws + cw.z0), *P0 = (float *)(ws + cw.parts0);
+    float *Z1 = (float *)(ws + cw.z1), *P1 = (float *)(ws + cw.parts1);
     const int64_t ldwy = Q ? n : b;
-
     const int64_t np = (n + b - 1) / b;
-    // split-K descriptors: W^T A_r of every panel, then Y^T Q of the Q pass
+    auto wpan = [&](int64_t jp) { return Q ? Wb + jp * b * (n + 1) : Wb + (jp & 1) * m * b; };
+    auto ypan = [&](int64_t jp) { return Q ? Yb + jp * b * (n + 1) : Yb + (jp & 1) * m * b; };
+
+    // Look-ahead: panel j's reflector is applied first to panel j + 1's
+    // columns on the caller's stream (the critical path: the next panel is
+    // factored right after), and to the columns beyond on a second stream,
+    // where it overlaps the next panels' factorisations.  The next-panel
+    // update of panel j waits for the trailing update of panel j - 1 (which
+    // covers those columns); a trailing update waits for its panel's W and Y.
     SplitBatch sb;
+    std::vector<int> zn(np, -1), zt(np, -1), zq(np, -1);
     for (int64_t jp = 0; jp < np; ++jp) {
         const int64_t c = jp * b, ml = m - c;
         const int nc = (int)std::min<int64_t>(b, n - c);
-        const int64_t nr = n - c - nc;
-        const float *W = Q ? Wb + c * n + c : Wb;
-        if (nr > 0)
-            add_split(sb, pr, W, ldwy, A + c * lda + c + nc, lda, nc, nr, ml, Z, parts,
+        const int64_t nx = c + nc, nc2 = std::min<int64_t>(b, n - nx), rest = nx + nc2;
+        if (nc2 > 0) {
+            zn[jp] = (int)sb.gemms.size();
+            add_split(sb, pr, wpan(jp), ldwy, A + c * lda + nx, lda, nc, nc2, ml, Z0, P0,
                       ctx->num_cus);
+        }
+        if (rest < n) {
+            zt[jp] = (int)sb.gemms.size();
+            add_split(sb, pr, wpan(jp), ldwy, A + c * lda + rest, lda, nc, n - rest, ml, Z1, P1,
+                      ctx->num_cus);
+        }
     }
-    const int nz = (int)sb.gemms.size();
     if (Q)
         for (int64_t jp = np - 1; jp >= 0; --jp) {
             const int64_t c = jp * b, ml = m - c;
             const int nc = (int)std::min<int64_t>(b, n - c);
-            add_split(sb, pr, Yb + c * n + c, n, Q + c * ldq + c, ldq, nc, n - c, ml, Z, parts,
+            zq[jp] = (int)sb.gemms.size();
+            add_split(sb, pr, ypan(jp), n, Q + c * ldq + c, ldq, nc, n - c, ml, Z1, P1,
                       ctx->num_cus);
         }
     if (sb.probs.size() * sizeof(GemmDesc) > cw.items - cw.probs ||
@@ -963,43 +995,66 @@ la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, 
                               hipMemcpyHostToDevice, s),
                "la_caqr: items");
     }
+    LookAhead la;
+    LA_HIP(hipStreamCreateWithFlags(&la.s1, hipStreamNonBlocking), "la_caqr: stream");
+    LA_HIP(hipEventCreateWithFlags(&la.wy_ready, hipEventDisableTiming), "la_caqr: event");
+    LA_HIP(hipEventCreateWithFlags(&la.trail_done, hipEventDisableTiming), "la_caqr: event");
+    // the second stream starts after everything already queued on the caller's
+    LA_HIP(hipEventRecord(la.wy_ready, s), "la_caqr: record");
+    LA_HIP(hipStreamWaitEvent(la.s1, la.wy_ready, 0), "la_caqr: wait");
 
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
     LA_HIP(hipGetLastError(), "la_caqr: clear");
-    int zi = 0;
+    bool trail_pending = false;   // a trailing update was queued since the last wait on it
     for (int64_t jp = 0; jp < np; ++jp) {
         const int64_t c = jp * b, ml = m - c;
         const int nc = (int)std::min<int64_t>(b, n - c);
-        const int64_t nr = n - c - nc;
+        const int64_t nx = c + nc, nc2 = std::min<int64_t>(b, n - nx), rest = nx + nc2;
         float *Ap = A + c * lda + c;
-        float *W = Q ? Wb + c * n + c : Wb;
-        float *Y = Q ? Yb + c * n + c : Yb;
+        float *W = wpan(jp), *Y = ypan(jp);
         const TsqrPlan tp = tsqr_plan(ml, nc);
         LA_HIP(tsqr_run(Ap, lda, nc, Qr, b, Rr, b, ws + cw.tree, tp, s), "la_caqr: tsqr");
         LA_HIP(wy_run(ml, nc, Qr, b, W, ldwy, Y, ldwy, Minv, flag, s), "la_caqr: wy");
         hipLaunchKernelGGL(place_r_kernel, dim3(grid1d(ml * nc)), dim3(256), 0, s, Ap, lda, ml,
                            nc, (const float *)Rr, (int64_t)b);
         LA_HIP(hipGetLastError(), "la_caqr: place R");
-        if (nr > 0) {
-            // A_r <- Q_f^T A_r = A_r - Y (W^T A_r)
-            LA_HIP(run_split(pr, sb, zi++, probs_dev, items_dev, ctx->num_cus, s),
-                   "la_caqr: W^T A_r");
-            LA_HIP(gemm_sub(pr, Y, ldwy, Z, ml, nr, nc, Ap + nc, lda, s), "la_caqr: update");
+        if (rest < n)
+            LA_HIP(hipEventRecord(la.wy_ready, s), "la_caqr: record");
+        if (nc2 > 0) {
+            if (trail_pending) {
+                LA_HIP(hipStreamWaitEvent(s, la.trail_done, 0), "la_caqr: wait");
+                trail_pending = false;
+            }
+            // next panel's columns <- Q_f^T (...) = (...) - Y (W^T (...))
+            LA_HIP(run_split(pr, sb, zn[jp], probs_dev, items_dev, ctx->num_cus, s),
+                   "la_caqr: W^T A_next");
+            LA_HIP(gemm_sub(pr, Y, ldwy, Z0, ml, nc2, nc, A + c * lda + nx, lda, s),
+                   "la_caqr: next-panel update");
+        }
+        if (rest < n) {
+            LA_HIP(hipStreamWaitEvent(la.s1, la.wy_ready, 0), "la_caqr: wait");
+            LA_HIP(run_split(pr, sb, zt[jp], probs_dev, items_dev, ctx->num_cus, la.s1),
+                   "la_caqr: W^T A_rest");
+            LA_HIP(gemm_sub(pr, Y, ldwy, Z1, ml, n - rest, nc, A + c * lda + rest, lda, la.s1),
+                   "la_caqr: trailing update");
+            LA_HIP(hipEventRecord(la.trail_done, la.s1), "la_caqr: record");
+            trail_pending = true;
         }
     }
+    // join: the caller's stream continues after the last trailing update
+    LA_HIP(hipEventRecord(la.trail_done, la.s1), "la_caqr: record");
+    LA_HIP(hipStreamWaitEvent(s, la.trail_done, 0), "la_caqr: wait");
     if (Q) {
         hipLaunchKernelGGL(eye_kernel, dim3(grid1d(m * n)), dim3(256), 0, s, Q, ldq, m, n);
         LA_HIP(hipGetLastError(), "la_caqr: eye");
-        int qi = nz;
         for (int64_t jp = np - 1; jp >= 0; --jp) {
             const int64_t c = jp * b, ml = m - c;
             const int nc = (int)std::min<int64_t>(b, n - c);
-            const int64_t cols = n - c;
             float *Qc = Q + c * ldq + c;
             // Q[c:, c:] <- Q_f Q[c:, c:] = Q[c:, c:] - W (Y^T Q[c:, c:])
-            LA_HIP(run_split(pr, sb, qi++, probs_dev, items_dev, ctx->num_cus, s),
+            LA_HIP(run_split(pr, sb, zq[jp], probs_dev, items_dev, ctx->num_cus, s),
                    "la_caqr: Y^T Q");
-            LA_HIP(gemm_sub(pr, Wb + c * n + c, n, Z, ml, cols, nc, Qc, ldq, s), "la_caqr: Q");
+            LA_HIP(gemm_sub(pr, wpan(jp), n, Z1, ml, n - c, nc, Qc, ldq, s), "la_caqr: Q");
         }
     }
     return read_flag(flag, s, who);
