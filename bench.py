@@ -244,7 +244,7 @@ def matfunc_section(la, torch, n=8192, degree=16, seed=701):
     return out
 
 
-def qr_section(la, torch, n=8192, panel=64, tall=(131072, 64), seed=801):
+def qr_section(la, torch, n=16384, panel=64, tall=(131072, 64), seed=801):
     """Algorithm caqr on an n x n Gaussian A (R alone, then R and Q) at AUTO
     (6xBF16 updates) and all-FP32 MFMA, and Algorithm tsqr of a tall panel.
     Rates use the Householder operation counts: 4/3 n^3 for R, as much again
