@@ -3,7 +3,8 @@
 // la_tsqr -- Algorithm tsqr for an m x n panel, n <= 128.  The rows are cut
 //            into blocks of at most 256 rows (each with at least n rows).
 //            One workgroup factors one block by Householder reflections with
-//            the block resident in LDS, writes its R and forms its Q in place.
+//            the block resident in registers (each wave owns whole columns),
+//            writes its R and forms its Q in place.
 //            The R factors are stacked and factored again the same way (a
 //            256-row block holds 256 / n of them, so the tree reduces by that
 //            factor per level rather than pairwise) until one R remains.  The
@@ -15,7 +16,9 @@
 //            in one workgroup, then one row-parallel product.
 // la_caqr -- Algorithm caqr (right-looking): per panel of b columns, la_tsqr,
 //            la_wy, A_l <- [R; 0] and A_r <- A_r - Y (W^T A_r) as two GEMM
-//            launches (the first split along its long K = rows dimension);
+//            launches (the first split along its long K = rows dimension),
+//            with one panel of look-ahead: the next panel's columns are
+//            updated on the caller's stream and the rest on a second stream;
 //            optionally Q = Q_f(0) ... Q_f(last) [I; 0] afterwards.  AUTO runs
 //            the products as 6xBF16: the update's K is only the panel width,
 //            too short for the 3xBF16 products' per-term error (about 2^-16
@@ -112,7 +115,7 @@ __device__ inline T group_sum(T v)
 // Reflection j uses u = x - beta e_j (x = column j from row j down,
 // beta = -sign(x_j) ||x||, norm in FP64) unscaled, H_j = I - kappa u u^T,
 // kappa = 1 / (beta (beta - x_j)).  The owners of column j form u (zero above
-// row j, u_j = x_j - beta below it x) and publish it to one of two LDS
+// row j, u_j = x_j - beta on it, x below it) and publish it to one of two LDS
 // buffers with kappa; after one barrier every column c > j forms u^T x_c and
 // x_c -= kappa (u^T x_c) u, and the owners of column j + 1 (already updated)
 // prepare the next reflection into the other buffer.  One barrier per step.
