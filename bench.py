@@ -259,9 +259,12 @@ def qr_section(la, torch, n=16384, panel=64, tall=(131072, 64), seed=801):
         for want_q in (False, True):
             ws = torch.empty(la.caqr_workspace_size(n, n, panel, want_q) + 256,
                              dtype=torch.uint8, device="cuda:0")
+            got = {}
+
             def run():
                 X.copy_(A)
-                la.caqr(X, panel=panel, want_q=want_q, inplace=True, prec=prec, workspace=ws)
+                got["Q"], _ = la.caqr(X, panel=panel, want_q=want_q, inplace=True, prec=prec,
+                                      workspace=ws)
             run()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -269,9 +272,21 @@ def qr_section(la, torch, n=16384, panel=64, tall=(131072, 64), seed=801):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             flops = 4.0 / 3.0 * float(n) ** 3 * (2.0 if want_q else 1.0)
-            res["r_and_q" if want_q else "r_only"] = {
-                "seconds": round(dt, 4), "tflops_algorithmic": round(flops / dt / 1e12, 2)}
-            del ws
+            entry = {"seconds": round(dt, 4), "tflops_algorithmic": round(flops / dt / 1e12, 2)}
+            if want_q:
+                # FP64 probes (check only): ||A - QR||_F / ||A||_F and
+                # ||Q^T Q - I||_F / sqrt(n), from E||M g||^2 = ||M||_F^2, g ~ N(0, I)
+                pg = torch.randn((n, 16), dtype=torch.float64, device="cuda:0",
+                                 generator=torch.Generator(device="cuda:0").manual_seed(802))
+                Qd = got["Q"].double()
+                r1 = A.double() @ pg - Qd @ (torch.triu(X[:n]).double() @ pg)
+                entry["backward_probe"] = float(f"{float(torch.sqrt((r1 * r1).sum() / 16)) / float(torch.linalg.norm(A.double())):.3g}")
+                r2 = Qd.T @ (Qd @ pg) - pg
+                entry["orthogonality_probe"] = float(f"{float(torch.sqrt((r2 * r2).sum() / 16)) / n ** 0.5:.3g}")
+                del Qd, r1, r2, pg
+            res["r_and_q" if want_q else "r_only"] = entry
+            del ws, got
+            torch.cuda.empty_cache()
         out[name] = res
         print(f"[bench] caqr {name}: {res}", file=sys.stderr, flush=True)
     m, k = tall

@@ -259,3 +259,23 @@ def test_caqr_full_size_4096(la):
         assert out[name][0] <= TOL and out[name][1] <= TOL
         del Q, R
     assert out["auto"][0] <= 1.5 * out["fp32"][0] + 1e-7
+
+
+def test_caqr_bench_size_16384(la):
+    """The bench configuration (16384², panel 64, AUTO, R and Q): backward
+    error and orthogonality by 16 FP64 probes on the GPU (the factors stay
+    on the device)."""
+    n = 16384
+    A = torch.randn((n, n), device="cuda", generator=torch.Generator(device="cuda").manual_seed(801))
+    Q, R = la.caqr(A, panel=64)
+    g = torch.randn((n, 16), dtype=torch.float64, device="cuda",
+                    generator=torch.Generator(device="cuda").manual_seed(802))
+    Qd = Q.double()
+    r1 = A.double() @ g - Qd @ (R.double() @ g)
+    back = float(torch.sqrt((r1 * r1).sum() / 16)) / float(torch.linalg.norm(A.double()))
+    del r1
+    r2 = Qd.T @ (Qd @ g) - g
+    orth = float(torch.sqrt((r2 * r2).sum() / 16)) / math.sqrt(n)
+    print(f"\n16384 caqr: backward ~{back:.3g} orth ~{orth:.3g}")
+    assert back <= TOL and orth <= TOL
+    assert torch.equal(torch.tril(R, -1), torch.zeros_like(R))
