@@ -16,17 +16,22 @@
  *   la_matfunc_odd / la_matfunc_cheb -- polynomial matrix functions of the
  *                singular values (eq. OddPoly) and of the eigenvalues by a
  *                Chebyshev series (eq. EigenvaluePolynomial, III.D);
+ *   la_tsqr / la_wy / la_caqr -- QR factorisation (III.B): Algorithm tsqr
+ *                for tall panels, the WY form of eq. (Yamamoto), and the
+ *                right-looking Algorithm caqr;
  *   la_serve_* -- a continuous-batching server of la_polar requests.
  *
  * Conventions (the paper is silent on all of them):
  *   - real FP32 data, ROW-MAJOR with explicit leading dimensions: element
  *     (i, j) of X with leading dimension ldx is X[i * ldx + j];
  *   - every matrix pointer passed to la_gemm / la_polar / la_inverse /
- *     la_matfunc_* is DEVICE memory owned by the caller; the library never
- *     frees or retains it;
+ *     la_matfunc_* / la_tsqr / la_wy / la_caqr is DEVICE memory owned by the
+ *     caller; the library never frees or retains it;
  *   - hip_stream is a hipStream_t (NULL = the legacy default stream); la_gemm
  *     only enqueues work, la_polar and la_inverse block on a per-iteration
- *     8-byte readback;
+ *     8-byte readback, the other calls return after their last kernel
+ *     (la_caqr also uses a second stream of its own, joined before it
+ *     returns);
  *   - no exceptions cross the ABI and nothing aborts: every call returns a
  *     la_status; la_last_error() gives a message for the calling thread.
  */
