@@ -643,6 +643,27 @@ __device__ __forceinline__ void tile_coords(const GemmDesc &d, int lin, int &tm,
     }
 }
 
+// Tile of a workgroup of a 256 x 256-tile launch (one workgroup per CU).
+// Workgroups reach the XCDs round-robin and each XCD runs 32 at a time, so the
+// 256 tiles in flight form one 16 x 16 block of tiles, each XCD a 4 x 8 part
+// of it: such a round reads 16 A and 16 B operand panels, and each XCD's 32
+// tiles share 4 A and 8 B panels in its L2; consecutive rounds move down the
+// tile rows, keeping their B panels.  (With every XCD sweeping its own band of
+// tile rows across all columns instead, the packed kernel fetched 1.6 times as
+// much from HBM.)  Other tile counts, and Gram launches, use the general order.
+__device__ __forceinline__ void round_tile_coords(const GemmDesc &d, int &tm, int &tn)
+{
+    if (kXcds == 8 && d.tiles_m % 16 == 0 && d.tiles_n % 16 == 0 && !d.gram) {
+        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+        const int r = i / 32, sl = i % 32;
+        const int sm = d.tiles_m / 16;
+        tm = 16 * (r % sm) + 4 * (x % 4) + sl % 4;
+        tn = 16 * (r / sm) + 8 * (x / 4) + sl / 4;
+    } else {
+        tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
+    }
+}
+
 template <int PREC>
 __device__ __forceinline__ void epilogue(const GemmDesc &d,
                                          f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
@@ -961,9 +982,11 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
 {
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
-    const int lin = xcd_remap(blockIdx.x, d.num_tiles);
     int tm, tn;
-    tile_coords(d, lin, tm, tn);
+    if (Cfg<PREC>::BM == 256)
+        round_tile_coords(d, tm, tn);
+    else
+        tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
     gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
 }
 
@@ -1243,26 +1266,6 @@ __device__ __forceinline__ void packed_stage(int ss, int nst, f32x16 (&acc)[Geo<
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Tile of this workgroup in the packed kernel.  Workgroups reach the XCDs
-// round-robin and each XCD runs 32 at a time, so with 256 x 256 tiles the 256
-// tiles in flight form one 16 x 16 block of tiles (each XCD a 4 x 8 part of it):
-// such a round reads 16 A and 16 B operand panels, and consecutive rounds move
-// down the tile rows, keeping their B panels.  (With every XCD sweeping its own
-// 8 tile rows across all columns instead, the A panels were read again in every
-// round.)  Other tile counts use the general order.
-__device__ __forceinline__ void packed_tile_coords(const GemmDesc &d, int &tm, int &tn)
-{
-    if (kXcds == 8 && d.tiles_m % 16 == 0 && d.tiles_n % 16 == 0 && !d.gram) {
-        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
-        const int r = i / 32, sl = i % 32;
-        const int sm = d.tiles_m / 16;
-        tm = 16 * (r % sm) + 4 * (x % 4) + sl % 4;
-        tn = 16 * (r / sm) + 8 * (x / 4) + sl / 4;
-    } else {
-        tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
-    }
-}
-
 // GEMM on packed operands: d.A / d.B point at the packed buffers, d.K is
 // the (unpadded) inner dimension; the epilogue is the common one.
 template <int P>
@@ -1274,7 +1277,7 @@ __global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
     __shared__ __attribute__((aligned(1024))) char smem[NS * G::stage_bytes];
     __shared__ double red[4];
     int tm, tn;
-    packed_tile_coords(d, tm, tn);
+    round_tile_coords(d, tm, tn);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w / 2, wn = w % 2;
     f32x16 acc[FM][FN];
