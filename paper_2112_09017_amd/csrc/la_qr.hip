@@ -841,9 +841,10 @@ la_status la_tsqr(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t
     la_status st = check_ws(workspace, ws_bytes, tp.bytes, who);
     if (st != LA_OK)
         return st;
-    const size_t qb = extent_bytes(m, n, ldq), rb = extent_bytes(n, n, ldr);
-    if (overlaps(Q, qb, A, extent_bytes(m, n, lda)) || overlaps(R, rb, A, extent_bytes(m, n, lda)) ||
-        overlaps(Q, qb, R, rb) || overlaps(Q, qb, workspace, tp.bytes) ||
+    const size_t ab = extent_bytes(m, n, lda), qb = extent_bytes(m, n, ldq),
+                 rb = extent_bytes(n, n, ldr);
+    if (overlaps(Q, qb, A, ab) || overlaps(R, rb, A, ab) || overlaps(Q, qb, R, rb) ||
+        overlaps(A, ab, workspace, tp.bytes) || overlaps(Q, qb, workspace, tp.bytes) ||
         overlaps(R, rb, workspace, tp.bytes)) {
         set_error("%s: A, Q, R and the workspace must not overlap", who);
         return LA_ERR_INVALID_ARG;
@@ -885,7 +886,8 @@ la_status la_wy(la_context *ctx, int64_t m, int64_t n, const float *Q, int64_t l
     const size_t qb = extent_bytes(m, n, ldq), wb = extent_bytes(m, n, ldw),
                  yb = extent_bytes(m, n, ldy);
     if (overlaps(W, wb, Q, qb) || overlaps(Y, yb, Q, qb) || overlaps(W, wb, Y, yb) ||
-        overlaps(W, wb, workspace, need) || overlaps(Y, yb, workspace, need)) {
+        overlaps(Q, qb, workspace, need) || overlaps(W, wb, workspace, need) ||
+        overlaps(Y, yb, workspace, need)) {
         set_error("%s: Q, W, Y and the workspace must not overlap", who);
         return LA_ERR_INVALID_ARG;
     }

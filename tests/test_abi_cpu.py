@@ -147,6 +147,22 @@ def test_qr_argument_validation_without_device(L):
     assert L.la_last_error() == b"la_caqr: NULL argument"
 
 
+def test_qr_rejects_workspace_over_inputs(L):
+    # The checks compare address ranges only and come before the context is
+    # read, so host addresses stand in for device ones (nothing is accessed).
+    buf = ctypes.create_string_buffer(1 << 22)
+    base = (ctypes.addressof(buf) + 255) & ~255
+    ctx = base
+    m, n = 300, 64
+    need = L.la_tsqr_workspace_size(m, n)
+    A, Q, R = base + (1 << 20), base + (2 << 20), base + (3 << 20)
+    assert L.la_tsqr(ctx, m, n, A, n, Q, n, R, n, A, need, None) == 1
+    assert b"must not overlap" in L.la_last_error()
+    wneed = L.la_wy_workspace_size(n)
+    assert L.la_wy(ctx, m, n, Q, n, A, n, R, n, Q, wneed, None) == 1
+    assert b"must not overlap" in L.la_last_error()
+
+
 def test_create_reports_missing_device(L):
     import torch
     if torch.cuda.is_available():
