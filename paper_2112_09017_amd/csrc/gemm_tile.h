@@ -22,6 +22,7 @@
 //     sum of (out - E)^2 for the step norm.
 #pragma once
 
+#include <atomic>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -621,16 +622,21 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb)
 
 // Logical tile index -> (tile row, tile column).  General: groups of 8 tile
 // rows, column-major inside a group.  Gram: upper-triangle tiles row by row.
+__device__ __forceinline__ void gram_tile(int lin, int nt, int &tm, int &tn)
+{
+    int r = 0, rem = lin;
+    while (rem >= nt - r) {
+        rem -= nt - r;
+        ++r;
+    }
+    tm = r;
+    tn = r + rem;
+}
+
 __device__ __forceinline__ void tile_coords(const GemmDesc &d, int lin, int &tm, int &tn)
 {
     if (d.gram) {
-        int r = 0, rem = lin;
-        while (rem >= d.tiles_n - r) {
-            rem -= d.tiles_n - r;
-            ++r;
-        }
-        tm = r;
-        tn = r + rem;
+        gram_tile(lin, d.tiles_n, tm, tn);
     } else {
         constexpr int G = 8;
         const int per_group = G * d.tiles_n;
@@ -983,10 +989,19 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
     int tm, tn;
-    if (Cfg<PREC>::BM == 256)
+    if (Cfg<PREC>::BM == 256) {
         round_tile_coords(d, tm, tn);
-    else
+    } else if (d.quarters) {
+        // quarter (blockIdx.x & 3) of large Gram tile tail_first + blockIdx.x / 4
+        int TM, TN;
+        gram_tile(d.tail_first + (int)(blockIdx.x >> 2), (d.tiles_n + 1) / 2, TM, TN);
+        tm = 2 * TM + (int)((blockIdx.x >> 1) & 1);
+        tn = 2 * TN + (int)(blockIdx.x & 1);
+        if (tm > tn || tm >= d.tiles_m || tn >= d.tiles_n)
+            return;   // below the diagonal or past the edge: nothing of it is written
+    } else {
         tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
+    }
     gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
 }
 
@@ -1329,11 +1344,63 @@ hipError_t launch_one(const GemmDesc &d, hipStream_t s)
     return hipGetLastError();
 }
 
+// Compute units of the current device (cached per device).
+inline int device_cu_count()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// A large-tile Gram launch runs one tile per CU at a time.  When its tile
+// count leaves a last round of at most a quarter of the CUs busy (N = 16384:
+// 2080 tiles = 8 rounds + 32), the whole rounds keep the large tiles and the
+// rest run in a second launch as 128 x 128 quarters, one small-tile round.
+// The small tile class takes the same K steps in the same order, so every
+// element is computed exactly as before.
+template <int PREC>
+bool split_gram_tail(const GemmDesc &d, GemmDesc &big, GemmDesc &tail)
+{
+    if (!d.gram || d.small || d.quarters)
+        return false;
+    const int cus = device_cu_count();
+    if (cus <= 0 || d.num_tiles <= cus)
+        return false;
+    const int rest = d.num_tiles % cus;
+    if (rest == 0 || 4 * rest > cus)
+        return false;
+    big = d;
+    big.num_tiles = d.num_tiles - rest;
+    tail = d;
+    tail.small = 1;
+    tail.tiles_m = (int)((d.M + Cfg<PREC | kSmall>::BM - 1) / Cfg<PREC | kSmall>::BM);
+    tail.tiles_n = (int)((d.N + Cfg<PREC | kSmall>::BN - 1) / Cfg<PREC | kSmall>::BN);
+    tail.quarters = 1;
+    tail.tail_first = big.num_tiles;
+    tail.num_tiles = 4 * rest;
+    return true;
+}
+
 template <int PREC>
 hipError_t launch_t(const GemmDesc &d, hipStream_t s)
 {
     if (d.num_tiles <= 0)
         return hipSuccess;
+    GemmDesc big, tail;
+    if (split_gram_tail<PREC>(d, big, tail)) {
+        const hipError_t e = launch_one<PREC>(big, s);
+        if (e != hipSuccess)
+            return e;
+        return launch_one<PREC | kSmall>(tail, s);
+    }
     return d.small ? launch_one<PREC | kSmall>(d, s) : launch_one<PREC>(d, s);
 }
 

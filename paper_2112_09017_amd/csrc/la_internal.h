@@ -43,6 +43,8 @@ struct GemmDesc {
     int tiles_m, tiles_n;
     int num_tiles;     // tiles launched (upper triangle only for gram)
     int small;         // 128 x 128 tiles (chosen from the problem's own shape)
+    int quarters;      // small tiles covering large Gram tiles tail_first.. (4 per tile)
+    int tail_first;
 };
 
 // Tile geometry of each precision and tile class.  Both tile classes use the
