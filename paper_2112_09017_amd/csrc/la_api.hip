@@ -529,6 +529,7 @@ const char *la_status_string(la_status s)
     case LA_ERR_TOO_LARGE: return "LA_ERR_TOO_LARGE";
     case LA_ERR_NOT_READY: return "LA_ERR_NOT_READY";
     case LA_ERR_UNKNOWN_REQUEST: return "LA_ERR_UNKNOWN_REQUEST";
+    case LA_ERR_BREAKDOWN: return "LA_ERR_BREAKDOWN";
     }
     return "LA_ERR_UNKNOWN_STATUS";
 }

@@ -507,7 +507,26 @@ void la_server::tick()
 
 void la_server::run()
 {
-    hipSetDevice(device);
+    if (hipSetDevice(device) != hipSuccess) {
+        // nothing can run on this thread: the server stops as after a device
+        // error (submit refuses new requests), and each request already queued
+        // ends with LA_ERR_DEVICE
+        std::unique_lock<std::mutex> g(mu);
+        fatal = LA_ERR_DEVICE;
+        for (;;) {
+            for (Req *r : queue) {
+                r->status = LA_ERR_DEVICE;
+                r->state = DONE;
+                r->t_done = now_s();
+                stats.failed++;
+            }
+            queue.clear();
+            cv.notify_all();
+            cv.wait(g, [&] { return stop || !queue.empty(); });
+            if (stop)
+                return;
+        }
+    }
     for (;;) {
         {
             std::unique_lock<std::mutex> g(mu);
@@ -562,9 +581,9 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
         e = hipHostMalloc((void **)&s->h_deltas, 4096 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         if (s->stream)
-            hipStreamDestroy(s->stream);
+            (void)hipStreamDestroy(s->stream);
         if (s->h_stage)
-            hipHostFree(s->h_stage);
+            (void)hipHostFree(s->h_stage);
         set_error("la_serve_create: %s", hipGetErrorString(e));
         return LA_ERR_DEVICE;
     }
@@ -622,7 +641,7 @@ la_status la_serve_submit(la_server *s, int64_t m, int64_t n, const float *A_hos
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&r->h_pinned, (size_t)n * n * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
-        if (r->io_pinned) hipHostFree(r->io_pinned);
+        if (r->io_pinned) (void)hipHostFree(r->io_pinned);
         set_error("la_serve_submit: pinned allocation failed: %s", hipGetErrorString(e));
         return LA_ERR_OUT_OF_MEMORY;
     }
@@ -668,8 +687,8 @@ la_status la_serve_poll(la_server *s, uint64_t id, float *U_host, float *H_host,
         *info = r->info;
     if (req_status)
         *req_status = r->status;
-    if (r->io_pinned) hipHostFree(r->io_pinned);
-    if (r->h_pinned) hipHostFree(r->h_pinned);
+    if (r->io_pinned) (void)hipHostFree(r->io_pinned);
+    if (r->h_pinned) (void)hipHostFree(r->h_pinned);
     return LA_OK;
 }
 
@@ -695,15 +714,16 @@ la_status la_serve_destroy(la_server *s)
     }
     if (s->worker.joinable())
         s->worker.join();
-    hipStreamSynchronize(s->stream);
+    // teardown: an error here has no caller to act on it
+    (void)hipStreamSynchronize(s->stream);
     for (auto &kv : s->all) {
         Req *r = kv.second.get();
-        if (r->io_pinned) hipHostFree(r->io_pinned);
-        if (r->h_pinned) hipHostFree(r->h_pinned);
+        if (r->io_pinned) (void)hipHostFree(r->io_pinned);
+        if (r->h_pinned) (void)hipHostFree(r->h_pinned);
     }
-    hipStreamDestroy(s->stream);
-    hipHostFree(s->h_stage);
-    hipHostFree(s->h_deltas);
+    (void)hipStreamDestroy(s->stream);
+    (void)hipHostFree(s->h_stage);
+    (void)hipHostFree(s->h_deltas);
     delete s;
     return LA_OK;
 }

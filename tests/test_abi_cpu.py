@@ -46,8 +46,13 @@ def test_library_is_built_for_gfx950():
 
 
 def test_status_strings(L):
-    assert L.la_status_string(0) == b"LA_OK"
-    assert L.la_status_string(4) == b"LA_ERR_NOT_CONVERGED"
+    # every status the header declares is named by la_status_string
+    header = open(HEADER).read()
+    enum = header[header.index("typedef enum {"):header.index("} la_status;")]
+    declared = re.findall(r"\b(LA_(?:OK|ERR_\w+))\s*=\s*(\d+)", enum)
+    assert len(declared) >= 12
+    for name, value in declared:
+        assert L.la_status_string(int(value)) == name.encode(), name
     assert L.la_status_string(999) == b"LA_ERR_UNKNOWN_STATUS"
 
 
