@@ -1005,6 +1005,26 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
     gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
 }
 
+// Split-K slices of one product in a single launch, so that they run side by
+// side: slice blockIdx.y takes the k rows [y slice_k, min(K, (y + 1) slice_k))
+// of the two k-major operands and writes its own output at C + y slice_stride,
+// computing exactly what a launch of that slice alone would.
+template <int PREC>
+__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_sliced_kernel(GemmDesc d)
+{
+    __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
+    __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
+    const int64_t k0 = (int64_t)blockIdx.y * d.slice_k;
+    const int64_t kl = d.K - k0 < d.slice_k ? d.K - k0 : d.slice_k;
+    d.A += k0 * d.lda;
+    d.B += k0 * d.ldb;
+    d.K = kl > 0 ? kl : 0;
+    d.C += (int64_t)blockIdx.y * d.slice_stride;
+    int tm, tn;
+    tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
+    gemm_tile<PREC, false, false>(d, tm, tn, smem, red);
+}
+
 // Persistent grouped kernel: workgroup b runs items b, b + grid, ...; each
 // item is one tile of one problem, computed exactly as gemm_kernel would.
 template <int PREC, bool AKC, bool BKC>
@@ -1390,10 +1410,22 @@ bool split_gram_tail(const GemmDesc &d, GemmDesc &big, GemmDesc &tail)
 }
 
 template <int PREC>
+hipError_t launch_sliced(const GemmDesc &d, hipStream_t s)
+{
+    if (d.a_kcontig || d.b_kcontig || d.slice_k <= 0 || d.slices > 65535)
+        return hipErrorInvalidValue;
+    dim3 grid(d.num_tiles, d.slices), block(Geo<PREC>::NT);
+    hipLaunchKernelGGL((gemm_sliced_kernel<PREC>), grid, block, 0, s, d);
+    return hipGetLastError();
+}
+
+template <int PREC>
 hipError_t launch_t(const GemmDesc &d, hipStream_t s)
 {
     if (d.num_tiles <= 0)
         return hipSuccess;
+    if (d.slices > 1)
+        return d.small ? launch_sliced<PREC | kSmall>(d, s) : launch_sliced<PREC>(d, s);
     GemmDesc big, tail;
     if (split_gram_tail<PREC>(d, big, tail)) {
         const hipError_t e = launch_one<PREC>(big, s);

@@ -118,16 +118,32 @@ la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan 
     return LA_OK;
 }
 
+// Split-K slices of a Gram whose tiles cannot fill the 256 CUs (the slices
+// run in one launch; each keeps at least 2048 of the K = m rows).
 int gram_splits(int64_t m, int64_t n, int prec)
 {
     const int64_t nb = (n + tile_n(prec) - 1) / tile_n(prec);
     const int64_t tiles = nb * (nb + 1) / 2;
     if (tiles >= 256)
         return 1;
-    int64_t sp = (512 + tiles - 1) / tiles;
-    sp = std::min<int64_t>(sp, m / 2048);
-    sp = std::min<int64_t>(sp, 16);
-    return (int)std::max<int64_t>(sp, 1);
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(16, m / 2048));
+    if (tiles >= 128) {
+        // large tiles, one per CU: take the count whose rounds of 256 tiles
+        // cost least per unit of K (N = 4096: 136 tiles x 15 slices = 2040,
+        // 8 rounds of K / 15, against 3 rounds of K / 4 with 4 slices)
+        int64_t best = 1, best_rounds = 1;
+        for (int64_t sp = 2; sp <= cap; ++sp) {
+            const int64_t rounds = (tiles * sp + 255) / 256;
+            if (rounds * best < best_rounds * sp) {
+                best = sp;
+                best_rounds = rounds;
+            }
+        }
+        return (int)best;
+    }
+    // small tiles: about two tiles per CU
+    const int64_t sp = (512 + tiles - 1) / tiles;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, cap));
 }
 
 size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -223,23 +239,26 @@ static hipError_t gram_step(int prec, const float *X, int64_t ldx, int64_t m, in
         gemm_finalize(d, prec);
         return launch_gemm(prec, d, s);
     }
-    const int64_t ks = (m + splits - 1) / splits;
-    for (int sp = 0; sp < splits; ++sp) {
-        const int64_t k0 = sp * ks;
-        const int64_t kl = std::min<int64_t>(ks, m - k0);
-        GemmDesc e = d;
-        e.A = X + k0 * ldx;
-        e.B = X + k0 * ldx;
-        e.C = w.parts + (size_t)sp * n * n;
-        e.ldc = n;
-        e.K = kl > 0 ? kl : 0;
-        e.alpha = 1.0f;
-        e.gamma = 0.0f;
-        gemm_finalize(e, prec);
-        hipError_t err = launch_gemm(prec, e, s);
-        if (err != hipSuccess)
-            return err;
-    }
+    // the slices run in one launch; slice sp sums k in [sp ks, (sp + 1) ks)
+    // into its own n x n part, and the parts are added in slice order
+    d.A = X;
+    d.B = X;
+    d.C = w.parts;
+    d.ldc = n;
+    d.K = m;
+    d.alpha = 1.0f;
+    d.gamma = 0.0f;
+    gemm_finalize(d, prec);
+    d.slices = splits;
+    d.slice_k = (m + splits - 1) / splits;
+    // whole K stages per slice where the last slice still gets rows
+    const int64_t k32 = (d.slice_k + 31) / 32 * 32;
+    if ((splits - 1) * k32 < m)
+        d.slice_k = k32;
+    d.slice_stride = n * n;
+    const hipError_t err = launch_gemm(prec, d, s);
+    if (err != hipSuccess)
+        return err;
     return launch_splitk_sym_reduce(w.parts, splits, n, alpha, gamma, P, n, s);
 }
 

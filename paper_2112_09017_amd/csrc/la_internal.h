@@ -45,6 +45,10 @@ struct GemmDesc {
     int small;         // 128 x 128 tiles (chosen from the problem's own shape)
     int quarters;      // small tiles covering large Gram tiles tail_first.. (4 per tile)
     int tail_first;
+    // split-K slices in one launch (k-major operands only): slice y takes k in
+    // [y slice_k, min(K, (y + 1) slice_k)) and writes C + y slice_stride
+    int slices;
+    int64_t slice_k, slice_stride;
 };
 
 // Tile geometry of each precision and tile class.  Both tile classes use the
