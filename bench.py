@@ -502,7 +502,7 @@ def main():
     ms, tflops = rates[head]
     kernel_tflops = flops / kernel_ms / 1e9 if kernel_ms else tflops
 
-    # headline result for the baseline check (recompute, untimed)
+    # the product once more, untimed, for the oracle's sampled-tile check
     if head == "BF16X3":
         la.gemm_ws(Ad, Bd, Cd, prec=la.Precision.BF16X3)
     else:
