@@ -42,8 +42,12 @@ static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 void gemm_finalize(GemmDesc &d, int prec)
 {
-    d.vec_a = aligned16(d.A) && (d.lda % 4 == 0);
-    d.vec_b = aligned16(d.B) && (d.ldb % 4 == 0);
+    // The interior loader keeps 32-bit element offsets of up to 255 rows (or 24
+    // k rows) from a 64-bit stage base; an operand with a longer leading
+    // dimension takes the guarded loader, which indexes in 64 bits.
+    constexpr int64_t kMaxFastLd = (int64_t)1 << 23;
+    d.vec_a = aligned16(d.A) && (d.lda % 4 == 0) && d.lda < kMaxFastLd;
+    d.vec_b = aligned16(d.B) && (d.ldb % 4 == 0) && d.ldb < kMaxFastLd;
     // small tiles when large ones would leave most CUs idle
     {
         const int64_t lm = (d.M + tile_m(prec) - 1) / tile_m(prec);
