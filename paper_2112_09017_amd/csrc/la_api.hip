@@ -156,8 +156,28 @@ struct PolarWs {
     double *tiles;   // per-tile step-norm partials
     double *sumsq;   // norm partials
     double *scal;    // [0] ||A||_F^2, [1] ||U' - U||_F^2
+    char *pk;        // packed 3xBF16 copies of U and P for the update (may be null)
     int splits;
 };
+
+// Whether a 3xBF16 update U P (m x n times n x n) takes the packed-operand
+// kernel: 256 x 256 tiles (at least 128 of them) and K = n >= 256, as in
+// la_gemm_ws.  The packed kernel computes every product exactly as the
+// unpacked one, so the choice never changes a result.
+static bool packed_update(int64_t m, int64_t n, int prec)
+{
+    if (prec != PREC_BF16X3 || n < 256)
+        return false;
+    const int64_t tiles = ((m + 255) / 256) * ((n + 255) / 256);
+    return tiles >= 128;
+}
+
+static size_t packed_update_bytes(const PolarPlan &p)
+{
+    if (!packed_update(p.m, p.n, p.prec_pre) && !packed_update(p.m, p.n, p.prec_ns))
+        return 0;
+    return align_up256(packed_x3_bytes(p.m, p.n)) + align_up256(packed_x3_bytes(p.n, p.n));
+}
 
 static int max_splits(const PolarPlan &p)
 {
@@ -188,6 +208,7 @@ size_t polar_workspace_bytes(const PolarPlan &p)
     b += align256(max_update_tiles(p) * sizeof(double));
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     b += align256(8 * sizeof(double));
+    b += packed_update_bytes(p);
     return b;
 }
 
@@ -210,6 +231,8 @@ static PolarWs carve(const PolarPlan &p, void *ws)
     w.sumsq = (double *)b;
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     w.scal = (double *)b;
+    b += align256(8 * sizeof(double));
+    w.pk = packed_update_bytes(p) ? b : nullptr;
     return w;
 }
 
@@ -265,7 +288,7 @@ static hipError_t gram_step(int prec, const float *X, int64_t ldx, int64_t m, in
 // Xn <- alpha X P + beta X (partials of (Xn - X)^2 per tile if tiles != null).
 static hipError_t update_step(int prec, const float *X, int64_t ldx, const float *P, int64_t n,
                               int64_t m, float alpha, float beta, float *Xn, int64_t ldxn,
-                              double *tiles, int *ntiles, hipStream_t s)
+                              double *tiles, int *ntiles, hipStream_t s, char *pk = nullptr)
 {
     GemmDesc d;
     memset(&d, 0, sizeof d);
@@ -290,6 +313,19 @@ static hipError_t update_step(int prec, const float *X, int64_t ldx, const float
     gemm_finalize(d, prec);
     if (ntiles)
         *ntiles = d.tiles_m * d.tiles_n;
+    if (pk && packed_update(m, n, prec) && !d.small) {
+        // pack op(A) = X (rows m, k = n contiguous) and op(B)^T = P^T (rows n,
+        // read from P's k-major rows): the elements the unpacked kernel reads
+        char *pa = pk, *pb = pk + align_up256(packed_x3_bytes(m, n));
+        hipError_t e = launch_pack_x3(X, ldx, 1, m, n, pa, s);
+        if (e == hipSuccess)
+            e = launch_pack_x3(P, n, 0, n, n, pb, s);
+        if (e != hipSuccess)
+            return e;
+        d.A = (const float *)pa;
+        d.B = (const float *)pb;
+        return launch_gemm_packed_x3(d, s);
+    }
     return launch_gemm(prec, d, s);
 }
 
@@ -836,7 +872,7 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
         LA_HIP(gram_step(p.prec_pre, buf[cur], ld[cur], m, n, (float)(-p.c), 1.0f, w.P, w, s),
                "la_polar: precondition gram");
         LA_HIP(update_step(p.prec_pre, buf[cur], ld[cur], w.P, n, m, (float)p.a, 0.0f,
-                           buf[cur ^ 1], ld[cur ^ 1], nullptr, nullptr, s),
+                           buf[cur ^ 1], ld[cur ^ 1], nullptr, nullptr, s, w.pk),
                "la_polar: precondition update");
         cur ^= 1;
         inf.iters_precond++;
@@ -854,7 +890,7 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
         LA_HIP(gram_step(prec, buf[cur], ld[cur], m, n, -1.0f, 1.0f, w.P, w, s),
                "la_polar: NS gram");
         LA_HIP(update_step(prec, buf[cur], ld[cur], w.P, n, m, 0.5f, 1.0f, buf[cur ^ 1],
-                           ld[cur ^ 1], w.tiles, &ntiles, s),
+                           ld[cur ^ 1], w.tiles, &ntiles, s, w.pk),
                "la_polar: NS update");
         LA_HIP(launch_reduce_fixed(w.tiles, ntiles, w.scal + 1, s), "la_polar: delta");
         LA_HIP(hipMemcpyAsync(h2 + 1, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s),
