@@ -160,23 +160,44 @@ struct PolarWs {
     int splits;
 };
 
-// Whether a 3xBF16 update U P (m x n times n x n) takes the packed-operand
-// kernel: 256 x 256 tiles (at least 128 of them) and K = n >= 256, as in
-// la_gemm_ws.  The packed kernel computes every product exactly as the
+// Whether an M x N x K product takes the packed-operand kernel inside an
+// iteration: 3xBF16 on 256 x 256 tiles (at least 128 of them) with K >= 256,
+// as in la_gemm_ws.  The packed kernel computes every product exactly as the
 // unpacked one, so the choice never changes a result.
-static bool packed_update(int64_t m, int64_t n, int prec)
+static bool packs(int prec, int64_t M, int64_t N, int64_t K)
 {
-    if (prec != PREC_BF16X3 || n < 256)
-        return false;
-    const int64_t tiles = ((m + 255) / 256) * ((n + 255) / 256);
-    return tiles >= 128;
+    return prec == PREC_BF16X3 && K >= 256 && ((M + 255) / 256) * ((N + 255) / 256) >= 128;
+}
+
+// Bytes of the packed op(A) and op(B)^T of such a product (0 if it does not pack).
+static size_t pack_bytes(int prec, int64_t M, int64_t N, int64_t K)
+{
+    if (!packs(prec, M, N, K))
+        return 0;
+    return align_up256(packed_x3_bytes(M, K)) + align_up256(packed_x3_bytes(N, K));
+}
+
+// Launch d, through the packed-operand kernel when it qualifies and pk (of at
+// least pack_bytes) is given: op(A) and op(B)^T are packed into pk first.
+static hipError_t gemm_packed_or_plain(int prec, GemmDesc d, char *pk, hipStream_t s)
+{
+    if (pk && !d.gram && !d.small && d.slices <= 1 && packs(prec, d.M, d.N, d.K)) {
+        char *pa = pk, *pb = pk + align_up256(packed_x3_bytes(d.M, d.K));
+        hipError_t e = launch_pack_x3(d.A, d.lda, d.a_kcontig, d.M, d.K, pa, s);
+        if (e == hipSuccess)
+            e = launch_pack_x3(d.B, d.ldb, d.b_kcontig, d.N, d.K, pb, s);
+        if (e != hipSuccess)
+            return e;
+        d.A = (const float *)pa;
+        d.B = (const float *)pb;
+        return launch_gemm_packed_x3(d, s);
+    }
+    return launch_gemm(prec, d, s);
 }
 
 static size_t packed_update_bytes(const PolarPlan &p)
 {
-    if (!packed_update(p.m, p.n, p.prec_pre) && !packed_update(p.m, p.n, p.prec_ns))
-        return 0;
-    return align_up256(packed_x3_bytes(p.m, p.n)) + align_up256(packed_x3_bytes(p.n, p.n));
+    return std::max(pack_bytes(p.prec_pre, p.m, p.n, p.n), pack_bytes(p.prec_ns, p.m, p.n, p.n));
 }
 
 static int max_splits(const PolarPlan &p)
@@ -313,20 +334,7 @@ static hipError_t update_step(int prec, const float *X, int64_t ldx, const float
     gemm_finalize(d, prec);
     if (ntiles)
         *ntiles = d.tiles_m * d.tiles_n;
-    if (pk && packed_update(m, n, prec) && !d.small) {
-        // pack op(A) = X (rows m, k = n contiguous) and op(B)^T = P^T (rows n,
-        // read from P's k-major rows): the elements the unpacked kernel reads
-        char *pa = pk, *pb = pk + align_up256(packed_x3_bytes(m, n));
-        hipError_t e = launch_pack_x3(X, ldx, 1, m, n, pa, s);
-        if (e == hipSuccess)
-            e = launch_pack_x3(P, n, 0, n, n, pb, s);
-        if (e != hipSuccess)
-            return e;
-        d.A = (const float *)pa;
-        d.B = (const float *)pb;
-        return launch_gemm_packed_x3(d, s);
-    }
-    return launch_gemm(prec, d, s);
+    return gemm_packed_or_plain(prec, d, pk, s);
 }
 
 // ------------------------------------------------------------------ inverse
@@ -398,7 +406,16 @@ struct InvWs {
     double *tiles;   // per-tile step-norm partials
     double *sumsq;   // norm partials
     double *scal;    // [0] ||A A^T||_F^2, [1] ||X' - X||_F^2
+    char *pk;        // packed 3xBF16 operands of the step's products (may be null)
 };
+
+// Packed operands of the larger of the two products of a step: R = A X
+// (r x r, K = m) or X A (K = n), then X R (m x n, K = n) or R X (K = m).
+static size_t inverse_pack_bytes(const InvPlan &p)
+{
+    const int64_t k1 = p.wide ? p.m : p.n, k2 = p.wide ? p.n : p.m;
+    return std::max(pack_bytes(p.prec, p.r, p.r, k1), pack_bytes(p.prec, p.m, p.n, k2));
+}
 
 static size_t inverse_workspace_bytes(const InvPlan &p)
 {
@@ -408,6 +425,7 @@ static size_t inverse_workspace_bytes(const InvPlan &p)
     b += align256(inverse_max_tiles(p) * sizeof(double));
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     b += align256(8 * sizeof(double));
+    b += inverse_pack_bytes(p);
     return b;
 }
 
@@ -424,6 +442,8 @@ static InvWs inverse_carve(const InvPlan &p, void *ws)
     w.sumsq = (double *)b;
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     w.scal = (double *)b;
+    b += align256(8 * sizeof(double));
+    w.pk = inverse_pack_bytes(p) ? b : nullptr;
     return w;
 }
 
@@ -459,7 +479,7 @@ static hipError_t inverse_step(const InvPlan &p, int prec, const float *A, int64
         d.K = p.n;
     }
     gemm_finalize(d, prec);
-    hipError_t e = launch_gemm(prec, d, s);
+    hipError_t e = gemm_packed_or_plain(prec, d, w.pk, s);
     if (e != hipSuccess)
         return e;
 
@@ -493,7 +513,7 @@ static hipError_t inverse_step(const InvPlan &p, int prec, const float *A, int64
     }
     gemm_finalize(u, prec);
     *ntiles = u.tiles_m * u.tiles_n;
-    return launch_gemm(prec, u, s);
+    return gemm_packed_or_plain(prec, u, w.pk, s);
 }
 
 // Validation and descriptor of a la_gemm-style call.  *empty: nothing to do
