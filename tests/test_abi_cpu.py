@@ -181,3 +181,30 @@ def test_create_reports_missing_device(L):
 def test_destroy_accepts_null(L):
     assert L.la_destroy(None) == 0
     assert L.la_serve_destroy(None) == 0
+
+
+def test_workspace_sizes_follow_the_slice_and_pack_policies(L):
+    # host logic only: the sizes say how many split-K Gram parts la_polar keeps
+    # and whether it holds packed 3xBF16 copies for the update
+    from paper_2112_09017_amd._binding import InverseOpts, PolarOpts
+    MiB = 1 << 20
+    m, n = 131072, 4096
+    o = PolarOpts()
+    o.prec_ns = 1                       # FP32 NS steps: no step at 3xBF16
+    fp32_ns = L.la_polar_workspace_size(m, n, ctypes.byref(o))
+    auto = L.la_polar_workspace_size(m, n, None)
+    # 136 Gram tiles: 15 slices give 2040 workgroups, 8 rounds of 256 CUs
+    base = 4 * (m * n + n * n + 15 * n * n)
+    assert base <= fp32_ns < base + MiB
+    packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
+    assert base + packed <= auto < base + packed + MiB
+    # square 16384: 2080 Gram tiles, no slices; packed copies of U and P
+    m = n = 16384
+    base = 4 * (m * n + n * n)
+    packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
+    assert base + packed <= L.la_polar_workspace_size(m, n, None) < base + packed + MiB
+    # the inverse keeps the packed operands of the larger of its two products
+    assert base + packed <= L.la_inverse_workspace_size(n, n, None) < base + packed + MiB
+    io = InverseOpts()
+    io.prec = 1
+    assert base <= L.la_inverse_workspace_size(n, n, ctypes.byref(io)) < base + MiB
