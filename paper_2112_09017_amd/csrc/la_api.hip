@@ -178,18 +178,22 @@ static size_t pack_bytes(int prec, int64_t M, int64_t N, int64_t K)
 }
 
 // Launch d, through the packed-operand kernel when it qualifies and pk (of at
-// least pack_bytes) is given: op(A) and op(B)^T are packed into pk first.
-static hipError_t gemm_packed_or_plain(int prec, GemmDesc d, char *pk, hipStream_t s)
+// least pack_bytes) is given: op(A) and op(B)^T are packed into pk first,
+// unless an operand packed earlier is passed (pre_a / pre_b).
+static hipError_t gemm_packed_or_plain(int prec, GemmDesc d, char *pk, hipStream_t s,
+                                       const char *pre_a = nullptr, const char *pre_b = nullptr)
 {
     if (pk && !d.gram && !d.small && d.slices <= 1 && packs(prec, d.M, d.N, d.K)) {
         char *pa = pk, *pb = pk + align_up256(packed_x3_bytes(d.M, d.K));
-        hipError_t e = launch_pack_x3(d.A, d.lda, d.a_kcontig, d.M, d.K, pa, s);
-        if (e == hipSuccess)
+        hipError_t e = hipSuccess;
+        if (!pre_a)
+            e = launch_pack_x3(d.A, d.lda, d.a_kcontig, d.M, d.K, pa, s);
+        if (e == hipSuccess && !pre_b)
             e = launch_pack_x3(d.B, d.ldb, d.b_kcontig, d.N, d.K, pb, s);
         if (e != hipSuccess)
             return e;
-        d.A = (const float *)pa;
-        d.B = (const float *)pb;
+        d.A = (const float *)(pre_a ? pre_a : pa);
+        d.B = (const float *)(pre_b ? pre_b : pb);
         return launch_gemm_packed_x3(d, s);
     }
     return launch_gemm(prec, d, s);
@@ -407,14 +411,28 @@ struct InvWs {
     double *sumsq;   // norm partials
     double *scal;    // [0] ||A A^T||_F^2, [1] ||X' - X||_F^2
     char *pk;        // packed 3xBF16 operands of the step's products (may be null)
+    char *pka;       // A packed once for the first product (may be null)
 };
 
 // Packed operands of the larger of the two products of a step: R = A X
-// (r x r, K = m) or X A (K = n), then X R (m x n, K = n) or R X (K = m).
-static size_t inverse_pack_bytes(const InvPlan &p)
+// (r x r, K = m) or X A (K = n), then X R (m x n, K = n) or R X (K = m);
+// and A itself, packed once, as op(A) of A X or op(B)^T of X A (r rows, K = m
+// or n).
+static size_t inverse_step_pack_bytes(const InvPlan &p)
 {
     const int64_t k1 = p.wide ? p.m : p.n, k2 = p.wide ? p.n : p.m;
     return std::max(pack_bytes(p.prec, p.r, p.r, k1), pack_bytes(p.prec, p.m, p.n, k2));
+}
+
+static size_t inverse_a_pack_bytes(const InvPlan &p)
+{
+    const int64_t k1 = p.wide ? p.m : p.n;
+    return packs(p.prec, p.r, p.r, k1) ? align_up256(packed_x3_bytes(p.r, k1)) : 0;
+}
+
+static size_t inverse_pack_bytes(const InvPlan &p)
+{
+    return inverse_step_pack_bytes(p) + inverse_a_pack_bytes(p);
 }
 
 static size_t inverse_workspace_bytes(const InvPlan &p)
@@ -443,7 +461,9 @@ static InvWs inverse_carve(const InvPlan &p, void *ws)
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     w.scal = (double *)b;
     b += align256(8 * sizeof(double));
-    w.pk = inverse_pack_bytes(p) ? b : nullptr;
+    w.pk = inverse_step_pack_bytes(p) ? b : nullptr;
+    b += inverse_step_pack_bytes(p);
+    w.pka = inverse_a_pack_bytes(p) ? b : nullptr;
     return w;
 }
 
@@ -479,7 +499,10 @@ static hipError_t inverse_step(const InvPlan &p, int prec, const float *A, int64
         d.K = p.n;
     }
     gemm_finalize(d, prec);
-    hipError_t e = gemm_packed_or_plain(prec, d, w.pk, s);
+    // A was packed once for the step precision (the polish step does not pack)
+    const char *pre = prec == p.prec ? w.pka : nullptr;
+    hipError_t e = gemm_packed_or_plain(prec, d, w.pk, s, p.wide ? pre : nullptr,
+                                        p.wide ? nullptr : pre);
     if (e != hipSuccess)
         return e;
 
@@ -1072,6 +1095,9 @@ la_status la_inverse(la_context *ctx, int64_t n, int64_t m, const float *A, int6
     int64_t ld[2] = {ldx, n};
     int cur = 0;
     LA_HIP(launch_transpose_scale(A, lda, buf[cur], ld[cur], n, m, a, s), "la_inverse: X0");
+    if (w.pka)   // A as op(A) of A X (k contiguous) or as op(B)^T of X A (k-major)
+        LA_HIP(launch_pack_x3(A, lda, p.wide ? 1 : 0, p.r, p.wide ? p.m : p.n, w.pka, s),
+               "la_inverse: pack A");
 
     const double scale = p.literal ? 1.0 : sqrt(a);
     double eps = p.eps;

@@ -203,7 +203,9 @@ def test_workspace_sizes_follow_the_slice_and_pack_policies(L):
     base = 4 * (m * n + n * n)
     packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
     assert base + packed <= L.la_polar_workspace_size(m, n, None) < base + packed + MiB
-    # the inverse keeps the packed operands of the larger of its two products
+    # the inverse keeps the packed operands of the larger of its two products,
+    # and A packed once
+    packed += L.la_pack_size(n, n)
     assert base + packed <= L.la_inverse_workspace_size(n, n, None) < base + packed + MiB
     io = InverseOpts()
     io.prec = 1

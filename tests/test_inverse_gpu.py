@@ -211,3 +211,27 @@ def test_full_size_8192(la):
         del X
     assert res["auto"] <= 2 * G * 100.0 ** 2
     assert res["auto"] <= 1.25 * res["fp32"]
+
+
+def test_tall_at_packed_size(la):
+    """8192 x 3072 (tall: the step forms X A, 3072^2 with K = 8192, so its 3xBF16
+    products run on packed operands, with A packed once as the k-major
+    operand), cond 100: ||X A - I||_F / sqrt(m) by probes, within the bound and
+    no worse than the all-FP32-MFMA policy's (1.25x)."""
+    n, m = 8192, 3072
+    A32, Q, s, V = la_inputs.polar_case_torch(n, m, 1e-2, (621, 622, 623))
+    del Q, V
+    Ad = torch.from_numpy(A32).to("cuda")
+    A = A32.astype(np.float64)
+    g = la_inputs.rng(171).standard_normal(size=(m, 32))
+    res = {}
+    for name, opts in (("auto", {}), ("fp32", dict(prec=1))):
+        X, info = la.inverse(Ad, **opts)
+        X = X.cpu().numpy().astype(np.float64)
+        assert X.shape == (m, n)
+        y = X @ (A @ g) - g
+        res[name] = math.sqrt(float(np.sum(y * y)) / g.shape[1]) / math.sqrt(m)
+        print(f"\n8192x3072 {name}: iters {info['iters']} residual ~{res[name]:.3g}")
+        assert info["stop_reason"] == 0
+    assert res["auto"] <= 2 * G * 100.0 ** 2
+    assert res["auto"] <= 1.25 * res["fp32"]
