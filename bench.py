@@ -108,6 +108,26 @@ def cpu_baseline(A, B, C_gpu, budget_s: float, seed: int = 203):
     }, float(est), tiles
 
 
+def polar_errors(torch, Ad, U, H, V, sd):
+    """Exact FP64 ||U^T U - I||_F / sqrt(n), ||A - U H||_F / ||A||_F and
+    ||H - V diag(s) V^T||_F / ||A||_F, by torch products on the GPU (checks
+    only, outside the timed region)."""
+    n = U.shape[1]
+    U64 = U.double()
+    G = U64.t().contiguous() @ U64
+    G.diagonal().sub_(1.0)
+    orth = torch.linalg.norm(G).item() / n ** 0.5
+    del G
+    A64 = Ad.double()
+    nA = torch.linalg.norm(A64).item()
+    resid = torch.linalg.norm(A64 - U64 @ H.double()).item() / nA
+    del A64, U64
+    dh = torch.linalg.norm(H.double() - (V * sd[None, :]) @ V.t().contiguous()).item() / nA
+    torch.cuda.empty_cache()
+    return {"orth": float(f"{orth:.3g}"), "resid": float(f"{resid:.3g}"),
+            "h_err": float(f"{dh:.3g}")}
+
+
 def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
     """Polar factorisation of an m x n A = Q diag(s) V^T (cond 1/lo), AUTO policy
     (6xBF16 preconditioning and H, 3xBF16 Newton-Schulz) and all-FP32-MFMA."""
@@ -115,8 +135,9 @@ def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
 
     t0 = time.perf_counter()
     A, Q, s, V = la_inputs.polar_case_torch(m, n, lo, seeds)
-    del Q, V
+    del Q
     torch.cuda.empty_cache()
+    sd = torch.from_numpy(s).to("cuda:0")
     Ad = torch.from_numpy(A).to("cuda:0")
     U = torch.empty_like(Ad)
     H = torch.empty((n, n), dtype=torch.float32, device="cuda:0")
@@ -139,6 +160,7 @@ def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
         out[name] = {"seconds": round(dt, 3), "iters_precond": info["iters_precond"],
                      "iters_ns": info["iters_ns"], "tflops_algorithmic": round(alg / dt / 1e12, 1),
                      "tflops_paper_equivalent": round(paper_eq / dt / 1e12, 1)}
+        out[name].update(polar_errors(torch, Ad, U, H, V, sd))
         print(f"[bench] polar {m}x{n} {name}: {dt:.2f} s, {out[name]}", file=sys.stderr,
               flush=True)
     out["speedup_auto_vs_fp32"] = round(out["fp32"]["seconds"] / out["auto"]["seconds"], 2)
@@ -419,6 +441,9 @@ def main():
     ap.add_argument("--no-qr", action="store_true")
     ap.add_argument("--qr-only", action="store_true",
                     help="run only the QR section (for profiling its kernels)")
+    ap.add_argument("--polar-only", action="store_true",
+                    help="run only the polar sections (16384^2 and, unless --no-tall, "
+                         "131072 x 4096), for profiling their kernels")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -447,6 +472,13 @@ def main():
 
     if args.qr_only:
         print(json.dumps({"qr": qr_section(la, torch)}), flush=True)
+        return
+    if args.polar_only:
+        res = {"polar": polar_section(la, torch)}
+        torch.cuda.empty_cache()
+        if not args.no_tall:
+            res["polar_tall"] = polar_section(la, torch, 131072, 4096, 1e-4, (501, 502, 503))
+        print(json.dumps(res), flush=True)
         return
     if args.serving_only:
         pool = serving_pool(torch)

@@ -159,7 +159,12 @@ typedef struct {
     int polish;       /* 1: one extra Newton-Schulz step at BF16X6 after the
                          stop test                                          [0] */
     int no_stagnation;/* 1: disable the stagnation stop                     [0] */
-    int reserved[3];
+    int max_acc_k;    /* FP32 accumulation depth: a product of the iteration
+                         or of H whose inner dimension exceeds it is split
+                         along K into slices of at most this length (rounded
+                         up to a multiple of 32), each accumulated in FP32,
+                         and the slices are added in FP64           [4096] */
+    int reserved[2];
 } la_polar_opts;
 
 typedef struct {

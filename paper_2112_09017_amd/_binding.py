@@ -58,7 +58,8 @@ class PolarOpts(ctypes.Structure):
         ("prec_h", ctypes.c_int),
         ("polish", ctypes.c_int),
         ("no_stagnation", ctypes.c_int),
-        ("reserved", ctypes.c_int * 3),
+        ("max_acc_k", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
     ]
 
 
@@ -219,7 +220,7 @@ def context(device: int) -> ctypes.c_void_p:
 
 def make_opts(s_minus=0.0, s0=0.0, eps=0.0, max_iter=0, prec_precond=Precision.AUTO,
               prec_ns=Precision.AUTO, prec_h=Precision.AUTO, polish=False,
-              stagnation=True) -> PolarOpts:
+              stagnation=True, max_acc_k=0) -> PolarOpts:
     o = PolarOpts()
     o.s_minus = s_minus
     o.s0 = s0
@@ -230,6 +231,7 @@ def make_opts(s_minus=0.0, s0=0.0, eps=0.0, max_iter=0, prec_precond=Precision.A
     o.prec_h = int(prec_h)
     o.polish = 1 if polish else 0
     o.no_stagnation = 0 if stagnation else 1
+    o.max_acc_k = int(max_acc_k)
     return o
 
 

@@ -233,22 +233,74 @@ __global__ void symmetrize_kernel(float *H, int64_t ldh, int64_t n)
     H[j * ldh + i] = h;
 }
 
-__global__ void splitk_sym_reduce_kernel(const float *__restrict__ parts, int splits, int64_t n,
-                                         float alpha, float gamma, float *__restrict__ out,
-                                         int64_t ldo)
+// Split-K sums of a symmetric product: the slices hold only their upper
+// triangles (i <= j; what lies below is not read).  Block (bj, bi), bj >= bi,
+// adds the 64 x 64 tile (bi, bj) of the slices in FP64 in slice order,
+// applies the epilogue in FP64, rounds once, writes the tile and, through
+// LDS, its transpose at (bj, bi), so out is exactly symmetric and both
+// writes are coalesced.
+constexpr int kSymTile = 64;
+
+__global__ void __launch_bounds__(256) splitk_sym_reduce_kernel(
+    const float *__restrict__ parts, int splits, int64_t n, double alpha, double gamma,
+    float *__restrict__ out, int64_t ldo)
 {
+    const int64_t bi = blockIdx.y, bj = blockIdx.x;
+    if (bj < bi)
+        return;
+    __shared__ float t[kSymTile][kSymTile + 1];
     const int64_t nn = n * n;
-    for (int64_t r = blockIdx.y; r < n; r += gridDim.y)
-        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
-             c += (int64_t)gridDim.x * blockDim.x) {
-            float acc = 0.0f;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < kSymTile; r += 4) {
+        const int64_t i = bi * kSymTile + r, j = bj * kSymTile + tx;
+        if (i < n && j < n && i <= j) {
+            double acc = 0.0;
             for (int s = 0; s < splits; ++s)
-                acc += parts[s * nn + r * n + c];
-            float v = alpha * acc;
-            if (r == c)
-                v = v + gamma;
-            out[r * ldo + c] = v;
+                acc += (double)parts[s * nn + i * n + j];
+            double v = alpha * acc;
+            if (i == j)
+                v += gamma;
+            const float f = (float)v;
+            out[i * ldo + j] = f;
+            t[r][tx] = f;
         }
+    }
+    __syncthreads();
+    for (int r = ty; r < kSymTile; r += 4) {
+        const int64_t j = bj * kSymTile + r, i = bi * kSymTile + tx;   // out(j, i), i < j
+        if (i < n && j < n && i < j)
+            out[j * ldo + i] = t[tx][r];
+    }
+}
+
+// out = alpha sum_s part_s + beta E for an m x n product whose slices are
+// m x n row-major (ld n), with the FP64 partial sum of (out - E)^2 of block b
+// in step[b] (step may be null).  Every thread visits its elements in a fixed
+// order and the block sum is a fixed tree, so the partials are reproducible.
+__global__ void __launch_bounds__(kThreads) splitk_update_reduce_kernel(
+    const float *__restrict__ parts, int splits, int64_t m, int64_t n, double alpha, double beta,
+    const float *__restrict__ E, int64_t lde, float *__restrict__ out, int64_t ldo,
+    double *__restrict__ step)
+{
+    __shared__ double sh[kThreads / 64];
+    const int64_t mn = m * n;
+    double ss = 0.0;
+    for (int64_t r = blockIdx.x; r < m; r += gridDim.x)
+        for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+            double acc = 0.0;
+            for (int s = 0; s < splits; ++s)
+                acc += (double)parts[s * mn + r * n + c];
+            const double e = E ? (double)E[r * lde + c] : 0.0;
+            const float v = (float)(alpha * acc + beta * e);
+            out[r * ldo + c] = v;
+            const double df = (double)v - e;
+            ss += df * df;
+        }
+    if (step) {
+        const double t = block_sum(ss, sh);
+        if (threadIdx.x == 0)
+            step[blockIdx.x] = t;
+    }
 }
 
 dim3 grid2d(int64_t m, int64_t n)
@@ -341,13 +393,29 @@ hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n, float alpha,
-                                    float gamma, float *out, int64_t ldo, hipStream_t s)
+int splitk_update_num_partials() { return kSumsqBlocks; }
+
+hipError_t launch_splitk_update_reduce(const float *parts, int splits, int64_t m, int64_t n,
+                                       double alpha, double beta, const float *E, int64_t lde,
+                                       float *out, int64_t ldo, double *step, hipStream_t s)
+{
+    if (m == 0 || n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(splitk_update_reduce_kernel, dim3(kSumsqBlocks), dim3(kThreads), 0, s,
+                       parts, splits, m, n, alpha, beta, E, lde, out, ldo, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n, double alpha,
+                                    double gamma, float *out, int64_t ldo, hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(splitk_sym_reduce_kernel, grid2d(n, n), dim3(kThreads), 0, s, parts,
-                       splits, n, alpha, gamma, out, ldo);
+    const int64_t nb = (n + kSymTile - 1) / kSymTile;
+    if (nb > 65535)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(splitk_sym_reduce_kernel, dim3((unsigned)nb, (unsigned)nb), dim3(256), 0, s,
+                       parts, splits, n, alpha, gamma, out, ldo);
     return hipGetLastError();
 }
 

@@ -700,7 +700,7 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
                 if (row == col)
                     val = val + d.gamma;
                 d.C[row * d.ldc + col] = val;
-                if (d.gram && row != col)
+                if (d.gram && !d.gram_upper && row != col)
                     d.C[col * d.ldc + row] = val;
                 if (want_ss) {
                     const double df = (double)val - (double)ev;
@@ -1006,23 +1006,28 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
 }
 
 // Split-K slices of one product in a single launch, so that they run side by
-// side: slice blockIdx.y takes the k rows [y slice_k, min(K, (y + 1) slice_k))
-// of the two k-major operands and writes its own output at C + y slice_stride,
-// computing exactly what a launch of that slice alone would.
-template <int PREC>
+// side: slice blockIdx.y takes k in [y slice_k, min(K, (y + 1) slice_k)) and
+// writes its own output at C + y slice_stride, computing exactly what a launch
+// of that slice alone would.  slice_k is a multiple of the K stage, so every
+// slice but the last is made of whole stages and keeps the operands' 16-byte
+// alignment.
+template <int PREC, bool AKC, bool BKC>
 __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_sliced_kernel(GemmDesc d)
 {
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
     const int64_t k0 = (int64_t)blockIdx.y * d.slice_k;
     const int64_t kl = d.K - k0 < d.slice_k ? d.K - k0 : d.slice_k;
-    d.A += k0 * d.lda;
-    d.B += k0 * d.ldb;
+    d.A += AKC ? k0 : k0 * d.lda;
+    d.B += BKC ? k0 : k0 * d.ldb;
     d.K = kl > 0 ? kl : 0;
     d.C += (int64_t)blockIdx.y * d.slice_stride;
     int tm, tn;
-    tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
-    gemm_tile<PREC, false, false>(d, tm, tn, smem, red);
+    if (Cfg<PREC>::BM == 256)
+        round_tile_coords(d, tm, tn);
+    else
+        tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
+    gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
 }
 
 // Persistent grouped kernel: workgroup b runs items b, b + grid, ...; each
@@ -1303,6 +1308,9 @@ __device__ __forceinline__ void packed_stage(int ss, int nst, f32x16 (&acc)[Geo<
 
 // GEMM on packed operands: d.A / d.B point at the packed buffers, d.K is
 // the (unpadded) inner dimension; the epilogue is the common one.
+// With d.slices > 1, slice blockIdx.y takes the k blocks of [y slice_k,
+// min(K, (y + 1) slice_k)) (slice_k a multiple of 16) and writes C + y
+// slice_stride, as the split-K launch of the unpacked kernels does.
 template <int P>
 __global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
 {
@@ -1323,9 +1331,17 @@ __global__ void __launch_bounds__(256, 1) gemm_packed_kernel(GemmDesc d)
             acc[i][j] = f32x16{};
     const char *pa = reinterpret_cast<const char *>(d.A);
     const char *pb = reinterpret_cast<const char *>(d.B);
-    const int64_t kbt = (d.K + 15) / 16;
     const int64_t rba = (int64_t)tm * 8, rbb = (int64_t)tn * 8;
     const int64_t rbta = (int64_t)d.tiles_m * 8, rbtb = (int64_t)d.tiles_n * 8;
+    if (d.slices > 1) {
+        const int64_t k0 = (int64_t)blockIdx.y * d.slice_k;
+        const int64_t kl = d.K - k0 < d.slice_k ? d.K - k0 : d.slice_k;
+        pa += (k0 / 16) * packed_kstride(rbta);
+        pb += (k0 / 16) * packed_kstride(rbtb);
+        d.K = kl > 0 ? kl : 0;
+        d.C += (int64_t)blockIdx.y * d.slice_stride;
+    }
+    const int64_t kbt = (d.K + 15) / 16;
     const int nst = (int)kbt;
     const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_offset(smem));
     // first-product fragments of the current stage
@@ -1412,10 +1428,17 @@ bool split_gram_tail(const GemmDesc &d, GemmDesc &big, GemmDesc &tail)
 template <int PREC>
 hipError_t launch_sliced(const GemmDesc &d, hipStream_t s)
 {
-    if (d.a_kcontig || d.b_kcontig || d.slice_k <= 0 || d.slices > 65535)
+    if (d.slice_k <= 0 || d.slice_k % Cfg<PREC>::BK != 0 || d.slices > 65535)
         return hipErrorInvalidValue;
     dim3 grid(d.num_tiles, d.slices), block(Geo<PREC>::NT);
-    hipLaunchKernelGGL((gemm_sliced_kernel<PREC>), grid, block, 0, s, d);
+    if (d.a_kcontig && d.b_kcontig)
+        hipLaunchKernelGGL((gemm_sliced_kernel<PREC, true, true>), grid, block, 0, s, d);
+    else if (d.a_kcontig)
+        hipLaunchKernelGGL((gemm_sliced_kernel<PREC, true, false>), grid, block, 0, s, d);
+    else if (d.b_kcontig)
+        hipLaunchKernelGGL((gemm_sliced_kernel<PREC, false, true>), grid, block, 0, s, d);
+    else
+        hipLaunchKernelGGL((gemm_sliced_kernel<PREC, false, false>), grid, block, 0, s, d);
     return hipGetLastError();
 }
 
@@ -1502,8 +1525,11 @@ inline hipError_t launch_packed_x3(const GemmDesc &d, hipStream_t s)
 {
     if (d.num_tiles <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL((gemm_packed_kernel<PREC_BF16X3 | kPacked>), dim3(d.num_tiles), dim3(256),
-                       0, s, d);
+    const int sl = d.slices > 1 ? d.slices : 1;
+    if (sl > 1 && (d.slice_k <= 0 || d.slice_k % 16 != 0 || sl > 65535))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_packed_kernel<PREC_BF16X3 | kPacked>), dim3(d.num_tiles, sl),
+                       dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

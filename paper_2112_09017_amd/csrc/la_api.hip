@@ -70,6 +70,17 @@ bool valid_prec(int p)
 
 // ------------------------------------------------------------------ polar plan
 
+// FP32 accumulation depth.  Every product accumulates in FP32 on the matrix
+// cores, one rounding per MFMA, so the rounding error of an output grows with
+// the number of accumulation steps along K; inside the preconditioning steps
+// it is amplified (the polynomial's relative condition near sigma = 1 is about
+// 23 at s_- = 0.1).  The iteration's products with K above kMaxAccK are
+// therefore split along K into slices of at most kMaxAccK, each accumulated in
+// FP32, and the slices are added in FP64 in slice order and rounded once.
+// (la_polar_opts.max_acc_k overrides the depth.)
+constexpr int64_t kMaxAccK = 4096;
+
+
 la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan *out)
 {
     la_polar_opts o;
@@ -92,6 +103,11 @@ la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan 
     p.eps = o.eps > 0 ? o.eps : ldexp(1.0, -23);
     p.max_iter = o.max_iter > 0 ? o.max_iter : 100;
     p.polish = o.polish != 0;
+    if (o.max_acc_k < 0) {
+        set_error("la_polar_opts: max_acc_k must be >= 0");
+        return LA_ERR_INVALID_ARG;
+    }
+    p.max_acc = o.max_acc_k > 0 ? ((int64_t)o.max_acc_k + 31) / 32 * 32 : kMaxAccK;
     p.stagnation = o.no_stagnation == 0;
     if (!(p.s_minus < 1.0) || !isfinite(p.s0) || !isfinite(p.eps)) {
         set_error("la_polar_opts: need 0 < s_minus < 1 and finite s0, eps");
@@ -118,16 +134,35 @@ la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan 
     return LA_OK;
 }
 
-// Split-K slices of a Gram whose tiles cannot fill the 256 CUs (the slices
-// run in one launch; each keeps at least 2048 of the K = m rows).
-int gram_splits(int64_t m, int64_t n, int prec)
+int acc_splits(int64_t K, int64_t max_acc)
+{
+    const int64_t a = max_acc > 0 ? max_acc : kMaxAccK;
+    return K > a ? (int)std::min<int64_t>(65535, (K + a - 1) / a) : 1;
+}
+
+// Slices of K for a requested count: the slice length is a multiple of 32 (whole
+// K stages of every kernel), so the count that results may be smaller.
+static int slice_plan(int64_t K, int want, int64_t *slice_k)
+{
+    int64_t sk = (K + want - 1) / want;
+    sk = (sk + 31) / 32 * 32;
+    *slice_k = sk;
+    return (int)((K + sk - 1) / sk);
+}
+
+// Split-K slices of a Gram: enough to keep each slice's FP32 accumulation
+// within kMaxAccK, and, when the tiles cannot fill the 256 CUs, enough to
+// fill them (the slices run in one launch; each keeps at least 2048 of the
+// K = m rows).
+int gram_splits(int64_t m, int64_t n, int prec, int64_t max_acc)
 {
     const int64_t nb = (n + tile_n(prec) - 1) / tile_n(prec);
     const int64_t tiles = nb * (nb + 1) / 2;
-    if (tiles >= 256)
-        return 1;
+    int fill = 1;
     const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(16, m / 2048));
-    if (tiles >= 128) {
+    if (tiles >= 256) {
+        fill = 1;
+    } else if (tiles >= 128) {
         // large tiles, one per CU: take the count whose rounds of 256 tiles
         // cost least per unit of K (N = 4096: 136 tiles x 15 slices = 2040,
         // 8 rounds of K / 15, against 3 rounds of K / 4 with 4 slices)
@@ -139,11 +174,14 @@ int gram_splits(int64_t m, int64_t n, int prec)
                 best_rounds = rounds;
             }
         }
-        return (int)best;
+        fill = (int)best;
+    } else {
+        // small tiles: about two tiles per CU
+        const int64_t sp = (512 + tiles - 1) / tiles;
+        fill = (int)std::max<int64_t>(1, std::min<int64_t>(sp, cap));
     }
-    // small tiles: about two tiles per CU
-    const int64_t sp = (512 + tiles - 1) / tiles;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, cap));
+    int64_t sk = 0;
+    return slice_plan(m, std::max(fill, acc_splits(m, max_acc)), &sk);
 }
 
 size_t align_up256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -152,12 +190,12 @@ static size_t align256(size_t x) { return align_up256(x); }
 struct PolarWs {
     float *X;        // m x n, ld n: the iterate's second buffer
     float *P;        // n x n: I - c U^T U or I - U^T U
-    float *parts;    // splits x n x n split-K Gram slices (may be null)
-    double *tiles;   // per-tile step-norm partials
+    float *parts;    // split-K slices of a Gram, an update or H (may be null)
+    double *tiles;   // per-tile (or per-block) step-norm partials
     double *sumsq;   // norm partials
     double *scal;    // [0] ||A||_F^2, [1] ||U' - U||_F^2
     char *pk;        // packed 3xBF16 copies of U and P for the update (may be null)
-    int splits;
+    size_t parts_floats;
 };
 
 // Whether an M x N x K product takes the packed-operand kernel inside an
@@ -179,11 +217,12 @@ static size_t pack_bytes(int prec, int64_t M, int64_t N, int64_t K)
 
 // Launch d, through the packed-operand kernel when it qualifies and pk (of at
 // least pack_bytes) is given: op(A) and op(B)^T are packed into pk first,
-// unless an operand packed earlier is passed (pre_a / pre_b).
+// unless an operand packed earlier is passed (pre_a / pre_b).  K-slices of d
+// (d.slices > 1) run on whichever kernel is chosen.
 static hipError_t gemm_packed_or_plain(int prec, GemmDesc d, char *pk, hipStream_t s,
                                        const char *pre_a = nullptr, const char *pre_b = nullptr)
 {
-    if (pk && !d.gram && !d.small && d.slices <= 1 && packs(prec, d.M, d.N, d.K)) {
+    if (pk && !d.gram && !d.small && packs(prec, d.M, d.N, d.K)) {
         char *pa = pk, *pb = pk + align_up256(packed_x3_bytes(d.M, d.K));
         hipError_t e = hipSuccess;
         if (!pre_a)
@@ -204,16 +243,40 @@ static size_t packed_update_bytes(const PolarPlan &p)
     return std::max(pack_bytes(p.prec_pre, p.m, p.n, p.n), pack_bytes(p.prec_ns, p.m, p.n, p.n));
 }
 
-static int max_splits(const PolarPlan &p)
+// Slices of the update X P (K = n) and of each half of H (K = m).
+static int update_splits(const PolarPlan &p)
 {
-    return std::max(gram_splits(p.m, p.n, p.prec_pre),
-                    std::max(gram_splits(p.m, p.n, p.prec_ns),
-                             gram_splits(p.m, p.n, PREC_BF16X6)));
+    int64_t sk = 0;
+    return slice_plan(p.n, acc_splits(p.n, p.max_acc), &sk);
+}
+
+static int h_splits(const PolarPlan &p)
+{
+    int64_t sk = 0;
+    return slice_plan(p.m, acc_splits(p.m, p.max_acc), &sk);
+}
+
+// Floats of split-K slices the iteration and H need at most: a Gram's
+// slices (n x n each), an update's (m x n each, when its K = n is split),
+// and H's two sets of n x n slices (U^T A and A^T U).
+static size_t parts_floats(const PolarPlan &p)
+{
+    size_t f = 0;
+    for (int pr : {p.prec_pre, p.prec_ns, (int)PREC_BF16X6}) {
+        const int g = gram_splits(p.m, p.n, pr, p.max_acc);
+        if (g > 1)
+            f = std::max(f, (size_t)g * p.n * p.n);
+    }
+    const int u = update_splits(p);
+    if (u > 1)
+        f = std::max(f, (size_t)u * p.m * p.n);
+    f = std::max(f, (size_t)2 * h_splits(p) * p.n * p.n);
+    return f;
 }
 
 static size_t max_update_tiles(const PolarPlan &p)
 {
-    size_t t = 0;
+    size_t t = (size_t)splitk_update_num_partials();
     for (int pr : {PREC_FP32, PREC_BF16X3, PREC_BF16X6}) {
         const size_t tm = (size_t)((p.m + tile_m(pr, 1) - 1) / tile_m(pr, 1));
         const size_t tn = (size_t)((p.n + tile_n(pr, 1) - 1) / tile_n(pr, 1));
@@ -224,12 +287,10 @@ static size_t max_update_tiles(const PolarPlan &p)
 
 size_t polar_workspace_bytes(const PolarPlan &p)
 {
-    const int sp = max_splits(p);
     size_t b = 0;
     b += align256((size_t)p.m * p.n * sizeof(float));
     b += align256((size_t)p.n * p.n * sizeof(float));
-    if (sp > 1)
-        b += align256((size_t)sp * p.n * p.n * sizeof(float));
+    b += align256(parts_floats(p) * sizeof(float));
     b += align256(max_update_tiles(p) * sizeof(double));
     b += align256((size_t)sumsq_num_partials() * sizeof(double));
     b += align256(8 * sizeof(double));
@@ -241,16 +302,13 @@ static PolarWs carve(const PolarPlan &p, void *ws)
 {
     PolarWs w;
     char *b = (char *)ws;
-    w.splits = max_splits(p);
     w.X = (float *)b;
     b += align256((size_t)p.m * p.n * sizeof(float));
     w.P = (float *)b;
     b += align256((size_t)p.n * p.n * sizeof(float));
-    w.parts = nullptr;
-    if (w.splits > 1) {
-        w.parts = (float *)b;
-        b += align256((size_t)w.splits * p.n * p.n * sizeof(float));
-    }
+    w.parts_floats = parts_floats(p);
+    w.parts = (float *)b;
+    b += align256(w.parts_floats * sizeof(float));
     w.tiles = (double *)b;
     b += align256(max_update_tiles(p) * sizeof(double));
     w.sumsq = (double *)b;
@@ -261,60 +319,81 @@ static PolarWs carve(const PolarPlan &p, void *ws)
     return w;
 }
 
-// P <- alpha X^T X + gamma I (exactly symmetric), X m x n with leading dim ldx.
-static hipError_t gram_step(int prec, const float *X, int64_t ldx, int64_t m, int64_t n,
-                            float alpha, float gamma, float *P, const PolarWs &w,
-                            hipStream_t s)
+// X1^T X2 for K x n operands X1, X2 (row-major, leading dimensions ld1, ld2)
+// as about `want` K-slices in one Gram-mode launch: slice y writes the upper
+// triangle (i <= j) of its n x n part, the sum over its k range, at
+// parts + y n^2.  *count receives the number of slices.
+static hipError_t gram_slices(int prec, const float *X1, int64_t ld1, const float *X2,
+                              int64_t ld2, int64_t K, int64_t n, int want, float *parts,
+                              int *count, hipStream_t s)
 {
-    const int splits = std::min(gram_splits(m, n, prec), w.splits);
     GemmDesc d;
     memset(&d, 0, sizeof d);
+    d.A = X1;
+    d.B = X2;
     d.a_kcontig = 0;
     d.b_kcontig = 0;
-    d.lda = ldx;
-    d.ldb = ldx;
+    d.lda = ld1;
+    d.ldb = ld2;
     d.M = n;
     d.N = n;
+    d.K = K;
     d.gram = 1;
-    if (splits <= 1) {
+    d.gram_upper = 1;
+    d.C = parts;
+    d.ldc = n;
+    d.alpha = 1.0f;
+    gemm_finalize(d, prec);
+    d.slices = slice_plan(K, want, &d.slice_k);
+    d.slice_stride = n * n;
+    *count = d.slices;
+    return launch_gemm(prec, d, s);
+}
+
+// P <- alpha X^T X + gamma I (exactly symmetric), X m x n with leading dim ldx.
+static hipError_t gram_step(const PolarPlan &p, int prec, const float *X, int64_t ldx,
+                            double alpha, double gamma, float *P, const PolarWs &w,
+                            hipStream_t s)
+{
+    const int64_t m = p.m, n = p.n;
+    const int splits = gram_splits(m, n, prec, p.max_acc);
+    if (splits <= 1 || (size_t)splits * n * n > w.parts_floats) {
+        GemmDesc d;
+        memset(&d, 0, sizeof d);
+        d.a_kcontig = 0;
+        d.b_kcontig = 0;
+        d.lda = ldx;
+        d.ldb = ldx;
+        d.M = n;
+        d.N = n;
+        d.gram = 1;
         d.A = X;
         d.B = X;
         d.C = P;
         d.ldc = n;
         d.K = m;
-        d.alpha = alpha;
-        d.gamma = gamma;
+        d.alpha = (float)alpha;
+        d.gamma = (float)gamma;
         gemm_finalize(d, prec);
         return launch_gemm(prec, d, s);
     }
-    // the slices run in one launch; slice sp sums k in [sp ks, (sp + 1) ks)
-    // into its own n x n part, and the parts are added in slice order
-    d.A = X;
-    d.B = X;
-    d.C = w.parts;
-    d.ldc = n;
-    d.K = m;
-    d.alpha = 1.0f;
-    d.gamma = 0.0f;
-    gemm_finalize(d, prec);
-    d.slices = splits;
-    d.slice_k = (m + splits - 1) / splits;
-    // whole K stages per slice where the last slice still gets rows
-    const int64_t k32 = (d.slice_k + 31) / 32 * 32;
-    if ((splits - 1) * k32 < m)
-        d.slice_k = k32;
-    d.slice_stride = n * n;
-    const hipError_t err = launch_gemm(prec, d, s);
-    if (err != hipSuccess)
-        return err;
-    return launch_splitk_sym_reduce(w.parts, splits, n, alpha, gamma, P, n, s);
+    // the slices run in one launch; slice y sums k in [y ks, (y + 1) ks) into
+    // the upper triangle of its own n x n part, and the parts are added in
+    // slice order in FP64
+    int count = 0;
+    hipError_t e = gram_slices(prec, X, ldx, X, ldx, m, n, splits, w.parts, &count, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_splitk_sym_reduce(w.parts, count, n, alpha, gamma, P, n, s);
 }
 
-// Xn <- alpha X P + beta X (partials of (Xn - X)^2 per tile if tiles != null).
-static hipError_t update_step(int prec, const float *X, int64_t ldx, const float *P, int64_t n,
-                              int64_t m, float alpha, float beta, float *Xn, int64_t ldxn,
-                              double *tiles, int *ntiles, hipStream_t s, char *pk = nullptr)
+// Xn <- alpha X P + beta X (partials of (Xn - X)^2 in tiles if tiles != null;
+// *ntiles receives their count).
+static hipError_t update_step(const PolarPlan &p, int prec, const float *X, int64_t ldx,
+                              const float *P, double alpha, double beta, float *Xn, int64_t ldxn,
+                              double *tiles, int *ntiles, const PolarWs &w, hipStream_t s)
 {
+    const int64_t m = p.m, n = p.n;
     GemmDesc d;
     memset(&d, 0, sizeof d);
     d.A = X;
@@ -323,22 +402,58 @@ static hipError_t update_step(int prec, const float *X, int64_t ldx, const float
     d.B = P;
     d.ldb = n;
     d.b_kcontig = 0;
-    d.C = Xn;
-    d.ldc = ldxn;
     d.M = m;
     d.N = n;
     d.K = n;
-    d.alpha = alpha;
-    if (beta != 0.0f) {
+    const int splits = update_splits(p);
+    if (splits > 1 && (size_t)splits * m * n <= w.parts_floats) {
+        // K-slices into m x n parts, added in FP64 with the update applied
+        d.C = w.parts;
+        d.ldc = n;
+        d.alpha = 1.0f;
+        gemm_finalize(d, prec);
+        d.slices = slice_plan(n, splits, &d.slice_k);
+        d.slice_stride = m * n;
+        hipError_t e = gemm_packed_or_plain(prec, d, w.pk, s);
+        if (e != hipSuccess)
+            return e;
+        if (ntiles)
+            *ntiles = splitk_update_num_partials();
+        return launch_splitk_update_reduce(w.parts, d.slices, m, n, alpha, beta,
+                                           beta != 0.0 ? X : nullptr, ldx, Xn, ldxn, tiles, s);
+    }
+    d.C = Xn;
+    d.ldc = ldxn;
+    d.alpha = (float)alpha;
+    if (beta != 0.0) {
         d.E = X;
         d.lde = ldx;
-        d.beta = beta;
+        d.beta = (float)beta;
     }
     d.partials = tiles;
     gemm_finalize(d, prec);
     if (ntiles)
         *ntiles = d.tiles_m * d.tiles_n;
-    return gemm_packed_or_plain(prec, d, pk, s);
+    return gemm_packed_or_plain(prec, d, w.pk, s);
+}
+
+// H = (U^T A + A^T U) / 2 in one symmetric pass: the upper triangle of U^T A
+// and of A^T U = (U^T A)^T are accumulated as Gram-mode slices (each of at most
+// kMaxAccK rows of the K = m sum), and the 2 s slices are added in FP64 with
+// the factor 1/2 and written to both triangles, so H is exactly symmetric.
+static hipError_t h_step(const PolarPlan &p, const float *U, int64_t ldu, const float *A,
+                         int64_t lda, float *H, int64_t ldh, const PolarWs &w, hipStream_t s)
+{
+    const int64_t n = p.n;
+    const int want = h_splits(p);
+    int c1 = 0, c2 = 0;
+    hipError_t e = gram_slices(p.prec_h, U, ldu, A, lda, p.m, n, want, w.parts, &c1, s);
+    if (e != hipSuccess)
+        return e;
+    e = gram_slices(p.prec_h, A, lda, U, ldu, p.m, n, want, w.parts + (size_t)c1 * n * n, &c2, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_splitk_sym_reduce(w.parts, c1 + c2, n, 0.5, 0.0, H, ldh, s);
 }
 
 // ------------------------------------------------------------------ inverse
@@ -912,10 +1027,10 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
 
     // preconditioning: U <- a U (I - c U^T U), c = (4/27) a^2
     for (int i = 0; i < p.k_pre; ++i) {
-        LA_HIP(gram_step(p.prec_pre, buf[cur], ld[cur], m, n, (float)(-p.c), 1.0f, w.P, w, s),
+        LA_HIP(gram_step(p, p.prec_pre, buf[cur], ld[cur], -p.c, 1.0, w.P, w, s),
                "la_polar: precondition gram");
-        LA_HIP(update_step(p.prec_pre, buf[cur], ld[cur], w.P, n, m, (float)p.a, 0.0f,
-                           buf[cur ^ 1], ld[cur ^ 1], nullptr, nullptr, s, w.pk),
+        LA_HIP(update_step(p, p.prec_pre, buf[cur], ld[cur], w.P, p.a, 0.0, buf[cur ^ 1],
+                           ld[cur ^ 1], nullptr, nullptr, w, s),
                "la_polar: precondition update");
         cur ^= 1;
         inf.iters_precond++;
@@ -930,10 +1045,10 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
         const bool polishing = stopped;
         const int prec = polishing ? PREC_BF16X6 : p.prec_ns;
         int ntiles = 0;
-        LA_HIP(gram_step(prec, buf[cur], ld[cur], m, n, -1.0f, 1.0f, w.P, w, s),
+        LA_HIP(gram_step(p, prec, buf[cur], ld[cur], -1.0, 1.0, w.P, w, s),
                "la_polar: NS gram");
-        LA_HIP(update_step(prec, buf[cur], ld[cur], w.P, n, m, 0.5f, 1.0f, buf[cur ^ 1],
-                           ld[cur ^ 1], w.tiles, &ntiles, s, w.pk),
+        LA_HIP(update_step(p, prec, buf[cur], ld[cur], w.P, 0.5, 1.0, buf[cur ^ 1], ld[cur ^ 1],
+                           w.tiles, &ntiles, w, s),
                "la_polar: NS update");
         LA_HIP(launch_reduce_fixed(w.tiles, ntiles, w.scal + 1, s), "la_polar: delta");
         LA_HIP(hipMemcpyAsync(h2 + 1, w.scal + 1, sizeof(double), hipMemcpyDeviceToHost, s),
@@ -967,26 +1082,8 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
     if (cur != 0)
         LA_HIP(launch_copy(buf[cur], ld[cur], U, ldu, m, n, s), "la_polar: copy");
 
-    if (H) {
-        // H = (U^T A + A^T U) / 2
-        GemmDesc d;
-        memset(&d, 0, sizeof d);
-        d.A = U;
-        d.lda = ldu;
-        d.a_kcontig = 0;
-        d.B = A;
-        d.ldb = lda;
-        d.b_kcontig = 0;
-        d.C = H;
-        d.ldc = ldh;
-        d.M = n;
-        d.N = n;
-        d.K = m;
-        d.alpha = 1.0f;
-        gemm_finalize(d, p.prec_h);
-        LA_HIP(launch_gemm(p.prec_h, d, s), "la_polar: H");
-        LA_HIP(launch_symmetrize(H, ldh, n, s), "la_polar: symmetrize");
-    }
+    if (H)
+        LA_HIP(h_step(p, U, ldu, A, lda, H, ldh, w, s), "la_polar: H");
     LA_HIP(hipStreamSynchronize(s), "la_polar: final sync");
     if (info)
         *info = inf;

@@ -39,14 +39,16 @@ struct GemmDesc {
     float alpha, beta, gamma;
     int a_kcontig, b_kcontig;
     int gram;
+    int gram_upper;    // gram: write only the upper triangle (no mirror)
     int vec_a, vec_b;  // operand addresses allow 16-byte vector loads
     int tiles_m, tiles_n;
     int num_tiles;     // tiles launched (upper triangle only for gram)
     int small;         // 128 x 128 tiles (chosen from the problem's own shape)
     int quarters;      // small tiles covering large Gram tiles tail_first.. (4 per tile)
     int tail_first;
-    // split-K slices in one launch (k-major operands only): slice y takes k in
-    // [y slice_k, min(K, (y + 1) slice_k)) and writes C + y slice_stride
+    // split-K slices in one launch: slice y takes k in [y slice_k, min(K,
+    // (y + 1) slice_k)) and writes C + y slice_stride (slice_k a multiple of
+    // 32, so every slice but the last is whole K stages)
     int slices;
     int64_t slice_k, slice_stride;
 };
@@ -108,11 +110,20 @@ hipError_t launch_copy(const float *X, int64_t ldx, float *Y, int64_t ldy,
 // In place H <- (H + H^T) / 2 for an n x n matrix.
 hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s);
 // Split-K reduction for a symmetric (gram) output: out(i, j) =
-// alpha * sum_s part_s(i, j) + gamma * [i == j], summed over s in order;
-// parts are `splits` exactly symmetric n x n slices (row-major, ld n).
+// alpha * sum_s part_s(i, j) + gamma * [i == j], summed over s in order in
+// FP64 and rounded once; parts are `splits` exactly symmetric n x n slices
+// (row-major, ld n).
 hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n,
-                                    float alpha, float gamma, float *out,
+                                    double alpha, double gamma, float *out,
                                     int64_t ldo, hipStream_t s);
+// Split-K reduction of an m x n product: out = alpha * sum_s part_s + beta * E
+// (FP64, rounded once; E may be null), parts m x n row-major (ld n).  If step
+// is not null, FP64 partial sums of (out - E)^2 go to
+// step[0 .. splitk_update_num_partials()).
+int splitk_update_num_partials();
+hipError_t launch_splitk_update_reduce(const float *parts, int splits, int64_t m, int64_t n,
+                                       double alpha, double beta, const float *E, int64_t lde,
+                                       float *out, int64_t ldo, double *step, hipStream_t s);
 
 // Grouped fixed-order FP64 reduction: one workgroup per item,
 // out[0] = sum of parts[0..count) (same order as launch_reduce_fixed).
@@ -128,12 +139,15 @@ struct PolarPlan {
     int64_t m, n;
     double s_minus, s0, eps, a, c;
     int k_pre, max_iter, polish, stagnation;
+    int64_t max_acc;   // FP32 accumulation depth of the split-K products
     int prec_pre, prec_ns, prec_h;
 };
 la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts,
                      PolarPlan *out);
-// Number of split-K slices the Gram of an m x n iterate uses.
-int gram_splits(int64_t m, int64_t n, int prec);
+// Number of split-K slices the Gram of an m x n iterate uses, and the number
+// needed to keep an inner dimension K within the FP32 accumulation depth.
+int gram_splits(int64_t m, int64_t n, int prec, int64_t max_acc);
+int acc_splits(int64_t K, int64_t max_acc);
 size_t polar_workspace_bytes(const PolarPlan &p);
 
 // Thread-local error text.

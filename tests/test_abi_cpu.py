@@ -184,8 +184,10 @@ def test_destroy_accepts_null(L):
 
 
 def test_workspace_sizes_follow_the_slice_and_pack_policies(L):
-    # host logic only: the sizes say how many split-K Gram parts la_polar keeps
-    # and whether it holds packed 3xBF16 copies for the update
+    # host logic only: the sizes say how many split-K parts la_polar keeps
+    # (Gram, update and H slices of at most max_acc_k = 4096 rows of K each,
+    # or more slices to fill the CUs) and whether it holds packed 3xBF16 copies
+    # for the update
     from paper_2112_09017_amd._binding import InverseOpts, PolarOpts
     MiB = 1 << 20
     m, n = 131072, 4096
@@ -193,18 +195,33 @@ def test_workspace_sizes_follow_the_slice_and_pack_policies(L):
     o.prec_ns = 1                       # FP32 NS steps: no step at 3xBF16
     fp32_ns = L.la_polar_workspace_size(m, n, ctypes.byref(o))
     auto = L.la_polar_workspace_size(m, n, None)
-    # 136 Gram tiles: 15 slices give 2040 workgroups, 8 rounds of 256 CUs
-    base = 4 * (m * n + n * n + 15 * n * n)
+    # the Gram takes 32 slices of 4096 rows (more than the 15 that fill the
+    # CUs); H takes 32 slices of U^T A and 32 of A^T U: 64 n x n parts
+    base = 4 * (m * n + n * n + 64 * n * n)
     assert base <= fp32_ns < base + MiB
     packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
     assert base + packed <= auto < base + packed + MiB
-    # square 16384: 2080 Gram tiles, no slices; packed copies of U and P
+    # a deeper accumulation: 16 Gram slices (still at least the 15 that fill
+    # the CUs) and 2 x 16 for H
+    o.max_acc_k = 8192
+    base = 4 * (m * n + n * n + 32 * n * n)
+    assert base <= L.la_polar_workspace_size(m, n, ctypes.byref(o)) < base + MiB
+    o.max_acc_k = -1
+    assert L.la_polar_workspace_size(m, n, ctypes.byref(o)) == 0
+    # square 16384: Gram and update in 4 slices each, H in 2 x 4; packed
+    # copies of U and P for the 3xBF16 update
     m = n = 16384
-    base = 4 * (m * n + n * n)
+    base = 4 * (m * n + n * n + 8 * n * n)
     packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
     assert base + packed <= L.la_polar_workspace_size(m, n, None) < base + packed + MiB
+    # accumulation over the whole K: only H's two parts
+    o = PolarOpts()
+    o.max_acc_k = 16384
+    base2 = 4 * (m * n + n * n + 2 * n * n)
+    assert base2 + packed <= L.la_polar_workspace_size(m, n, ctypes.byref(o)) < base2 + packed + MiB
     # the inverse keeps the packed operands of the larger of its two products,
     # and A packed once
+    base = 4 * (m * n + n * n)
     packed += L.la_pack_size(n, n)
     assert base + packed <= L.la_inverse_workspace_size(n, n, None) < base + packed + MiB
     io = InverseOpts()

@@ -114,6 +114,51 @@ def test_tall_and_ragged(la, shape):
     assert np.linalg.norm(H - Ho) / nA <= TOL
 
 
+@pytest.mark.parametrize("policy", ["auto", "fp32", "x6"])
+@pytest.mark.parametrize("shape", [(300, 200), (1000, 37), (640, 256)])
+def test_split_k_paths_vs_oracle(la, policy, shape):
+    """A short FP32 accumulation depth (max_acc_k = 96) splits every Gram,
+    update and H product along K into slices with a ragged last one, added in
+    FP64: same tolerances against the oracle as the unsplit products."""
+    m, n = shape
+    case = la_inputs.polar_case(m, n, 1e-3, seeds=(130 + m, 131 + n, 132))
+    U, H, info = run(la, case.A32, max_acc_k=96, **POLICIES[policy])
+    orth, resid = metrics(case.A32, U, H)
+    Uo, Ho, _ = oracle.polar(case.A32.astype(np.float64))
+    nA = np.linalg.norm(case.A32.astype(np.float64))
+    s = np.sort(case.s)
+    u_bound = 2 * TOL * nA / (s[0] + s[1])
+    print(shape, policy, info, f"orth={orth:.2e} resid={resid:.2e}")
+    assert orth <= TOL and resid <= TOL
+    assert np.linalg.norm(H - Ho) / nA <= TOL
+    assert np.array_equal(H, H.T)
+    assert np.linalg.norm(U - Uo) <= u_bound
+
+
+def test_split_k_packed_update_by_fp64_properties(la):
+    """4096 x 2048 takes the packed 3xBF16 update (128 tiles of 256 x 256);
+    with max_acc_k = 512 its K = 2048 runs as four packed slices.  Checked by
+    FP64 products on the GPU (test tooling): orthogonality, residual and H
+    against V diag(s) V^T of the construction."""
+    m, n = 4096, 2048
+    A, Q, s, V = la_inputs.polar_case_torch(m, n, 1e-3, (141, 142, 143))
+    del Q
+    Ad = torch.from_numpy(A).to("cuda")
+    U, H, info = la.polar(Ad, max_acc_k=512)
+    torch.cuda.synchronize()
+    A64, U64, H64 = Ad.double(), U.double(), H.double()
+    orth = torch.linalg.norm(U64.t().contiguous() @ U64 - torch.eye(n, dtype=torch.float64,
+                                                                     device="cuda")).item()
+    orth /= math.sqrt(n)
+    nA = torch.linalg.norm(A64).item()
+    resid = torch.linalg.norm(A64 - U64 @ H64).item() / nA
+    sd = torch.from_numpy(s).to("cuda")
+    dh = torch.linalg.norm(H64 - (V * sd[None, :]) @ V.t().contiguous()).item() / nA
+    print(info, f"orth={orth:.2e} resid={resid:.2e} dH={dh:.2e}")
+    assert orth <= TOL and resid <= TOL and dh <= TOL
+    assert torch.equal(H, H.t())
+
+
 def test_h_against_exact_construction(la):
     """H = V diag(s) V^T is well conditioned even at cond 1e6."""
     case = la_inputs.polar_case(384, 384, 1e-6, seeds=(120, 121, 122))
