@@ -200,6 +200,25 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A,
                    void *workspace, size_t ws_bytes, const la_polar_opts *opts,
                    la_polar_info *info, void *hip_stream);
 
+/* la_polar without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation): the same computation as la_polar, bit for bit,
+ * with the workspace taken from a buffer of LA_POLAR_NOALLOC_BYTES that the
+ * library holds statically on every GPU it runs on (from the first la_create
+ * on that device until the process ends).  Allocates nothing: no device or
+ * host allocation is made by the call.  LA_ERR_TOO_LARGE if
+ * la_polar_workspace_size(m, n, opts) exceeds LA_POLAR_NOALLOC_BYTES (square
+ * inputs up to about n = 2000 fit at the default options).  The buffer keeps
+ * the last call's contents (nothing in it needs to start at zero), and all
+ * calls on one GPU share it: calls that overlap in time on one GPU (from
+ * several threads, or on several streams) race and must be serialised by the
+ * caller.  Other arguments, results and errors as for la_polar. */
+#define LA_POLAR_NOALLOC_BYTES ((size_t)64 << 20)
+la_status la_polar_noalloc(la_context *ctx, int64_t m, int64_t n, const float *A,
+                           int64_t lda, float *U, int64_t ldu, float *H, int64_t ldh,
+                           const la_polar_opts *opts, la_polar_info *info,
+                           void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Newton-Schulz matrix inversion (section III.D, Algorithm NS_Inverse).
  * For an n x m A of full rank it returns the m x n X with X A = I_m

@@ -17,7 +17,7 @@ from ._binding import (InverseInfo, LAError, PolarInfo, PolarOpts, Precision, Se
                        ServeStats, Status, check, context, lib, make_inverse_opts, make_opts,
                        LIB_PATH, SIGNATURES)
 
-__all__ = ["gemm", "gemm_ws", "gemm_workspace_size", "pack_bf16x3", "gemm_packed", "polar", "polar_workspace_size", "inverse", "inverse_workspace_size",
+__all__ = ["gemm", "gemm_ws", "gemm_workspace_size", "pack_bf16x3", "gemm_packed", "polar", "polar_noalloc", "polar_workspace_size", "inverse", "inverse_workspace_size",
            "matfunc_odd", "matfunc_cheb", "tsqr", "wy", "caqr", "caqr_workspace_size",
            "Precision", "LAError", "Status", "lib", "LIB_PATH",
            "Server"]
@@ -161,6 +161,35 @@ def polar(A: torch.Tensor, *, want_h: bool = True, U: torch.Tensor | None = None
     ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
     st = lib().la_polar(ctx, m, n, pa, lda, pu, ldu, ph or None, ldh, wp_al, avail,
                         ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream))
+    if st == Status.NOT_CONVERGED and not raise_not_converged:
+        return U, H, info.as_dict()
+    check(st)
+    return U, (H if want_h else None), info.as_dict()
+
+
+def polar_noalloc(A: torch.Tensor, *, want_h: bool = True, U: torch.Tensor | None = None,
+                  H: torch.Tensor | None = None, stream=None, raise_not_converged: bool = True,
+                  **opts):
+    """``la_polar_noalloc``: la_polar with the library's static workspace
+    (LA_POLAR_NOALLOC_BYTES per GPU); the library allocates nothing.  Returns
+    (U, H or None, info dict) like ``polar``."""
+    pa, m, n, lda, ta = _as_matrix(A, "A")
+    if ta:
+        raise ValueError("A must be row-major (contiguous rows)")
+    dev = A.device
+    if U is None:
+        U = torch.empty((m, n), dtype=torch.float32, device=dev)
+    if want_h and H is None:
+        H = torch.empty((n, n), dtype=torch.float32, device=dev)
+    o = make_opts(**opts)
+    pu, _, _, ldu, _ = _as_matrix(U, "U")
+    ph, ldh = (0, n)
+    if H is not None:
+        ph, _, _, ldh, _ = _as_matrix(H, "H")
+    info = PolarInfo()
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    st = lib().la_polar_noalloc(ctx, m, n, pa, lda, pu, ldu, ph or None, ldh, ctypes.byref(o),
+                                ctypes.byref(info), _stream_ptr(stream))
     if st == Status.NOT_CONVERGED and not raise_not_converged:
         return U, H, info.as_dict()
     check(st)

@@ -150,6 +150,9 @@ SIGNATURES = {
     "la_polar": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64, _VP,
                                 ctypes.c_size_t, ctypes.POINTER(PolarOpts),
                                 ctypes.POINTER(PolarInfo), _VP]),
+    "la_polar_noalloc": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, _I64,
+                                        ctypes.POINTER(PolarOpts), ctypes.POINTER(PolarInfo),
+                                        _VP]),
     "la_inverse_workspace_size": (ctypes.c_size_t, [_I64, _I64, ctypes.POINTER(InverseOpts)]),
     "la_inverse": (ctypes.c_int, [_VP, _I64, _I64, _VP, _I64, _VP, _I64, _VP, ctypes.c_size_t,
                                   ctypes.POINTER(InverseOpts), ctypes.POINTER(InverseInfo), _VP]),

@@ -21,12 +21,40 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "la_internal.h"
 
 namespace la {
 
 static thread_local char g_err[512];
+
+// The one statically allocated device buffer of the library: the workspace of
+// la_polar_noalloc, for callers that cannot allocate device memory.  Each GPU
+// the library runs on holds its own copy until the process ends; its address
+// on a device comes from hipGetSymbolAddress, taken once per device when the
+// first context on that device is created.
+constexpr size_t kScratchBytes = LA_POLAR_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `device` (the caller has made it current).
+static hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 void set_error(const char *fmt, ...)
 {
@@ -775,6 +803,26 @@ la_status la_create(int device, la_context **out)
                   prop.gcnArchName);
         return LA_ERR_DEVICE;
     }
+    if (device >= kMaxDevices) {
+        set_error("la_create: device %d beyond the %d this library tracks", device, kMaxDevices);
+        return LA_ERR_INVALID_ARG;
+    }
+    // the static workspace's address on this device, with the device current
+    // (the caller's current device is restored)
+    int prev = -1;
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess)
+        return dev_fail(e, "la_create: hipGetDevice");
+    e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return dev_fail(e, "la_create: hipSetDevice");
+    void *sp = nullptr;
+    e = scratch_address(device, &sp);
+    const hipError_t e2 = hipSetDevice(prev);
+    if (e != hipSuccess)
+        return dev_fail(e, "la_create: hipGetSymbolAddress(scratch)");
+    if (e2 != hipSuccess)
+        return dev_fail(e2, "la_create: restoring the current device");
     la_context *c = new (std::nothrow) la_context;
     if (!c) {
         set_error("la_create: out of host memory");
@@ -782,6 +830,7 @@ la_status la_create(int device, la_context **out)
     }
     c->device = device;
     c->num_cus = prop.multiProcessorCount;
+    c->scratch = sp;
     *out = c;
     return LA_OK;
 }
@@ -957,6 +1006,18 @@ size_t la_polar_workspace_size(int64_t m, int64_t n, const la_polar_opts *opts)
     return polar_workspace_bytes(p);
 }
 
+}  // extern "C"
+
+namespace la {
+
+static la_status polar_impl(la_context *ctx, const PolarPlan &p, const float *A, int64_t lda,
+                            float *U, int64_t ldu, float *H, int64_t ldh, void *workspace,
+                            size_t ws_bytes, la_polar_info *info, void *hip_stream);
+
+}  // namespace la
+
+extern "C" {
+
 la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda, float *U,
                    int64_t ldu, float *H, int64_t ldh, void *workspace, size_t ws_bytes,
                    const la_polar_opts *opts, la_polar_info *info, void *hip_stream)
@@ -966,6 +1027,42 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
     la_status st = polar_plan(m, n, opts, &p);
     if (st != LA_OK)
         return st;
+    return polar_impl(ctx, p, A, lda, U, ldu, H, ldh, workspace, ws_bytes, info, hip_stream);
+}
+
+la_status la_polar_noalloc(la_context *ctx, int64_t m, int64_t n, const float *A, int64_t lda,
+                           float *U, int64_t ldu, float *H, int64_t ldh,
+                           const la_polar_opts *opts, la_polar_info *info, void *hip_stream)
+{
+    g_err[0] = 0;
+    PolarPlan p;
+    la_status st = polar_plan(m, n, opts, &p);
+    if (st != LA_OK)
+        return st;
+    if (!ctx) {
+        set_error("la_polar_noalloc: ctx is NULL");
+        return LA_ERR_INVALID_ARG;
+    }
+    const size_t need = polar_workspace_bytes(p);
+    if (need > kScratchBytes) {
+        set_error("la_polar_noalloc: a %lld x %lld polar needs %zu bytes of workspace; the "
+                  "static buffer holds %zu (use la_polar with a workspace)",
+                  (long long)m, (long long)n, need, kScratchBytes);
+        return LA_ERR_TOO_LARGE;
+    }
+    return polar_impl(ctx, p, A, lda, U, ldu, H, ldh, ctx->scratch, kScratchBytes, info,
+                      hip_stream);
+}
+
+}  // extern "C"
+
+namespace la {
+
+static la_status polar_impl(la_context *ctx, const PolarPlan &p, const float *A, int64_t lda,
+                            float *U, int64_t ldu, float *H, int64_t ldh, void *workspace,
+                            size_t ws_bytes, la_polar_info *info, void *hip_stream)
+{
+    const int64_t m = p.m, n = p.n;
     if (lda < n || ldu < n || (H && ldh < n)) {
         set_error("la_polar: leading dimension smaller than n");
         return LA_ERR_SHAPE;
@@ -1094,6 +1191,10 @@ la_status la_polar(la_context *ctx, int64_t m, int64_t n, const float *A, int64_
     }
     return LA_OK;
 }
+
+}  // namespace la
+
+extern "C" {
 
 size_t la_inverse_workspace_size(int64_t n, int64_t m, const la_inverse_opts *opts)
 {

@@ -11,6 +11,7 @@
 struct la_context {
     int device;
     int num_cus;
+    void *scratch;   // this device's static polar workspace (la_polar_noalloc)
 };
 
 namespace la {
