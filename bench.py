@@ -343,15 +343,36 @@ def serving_pool(torch, pool_size=48, seed=401):
     return pool
 
 
-def serving_section(la, pool, rate=100.0, duration=10.0, seed=401, exclude_s=1.0):
+def served_errors(torch, A, U, H):
+    """FP64 orthogonality and residual of one served result (check only)."""
+    n = U.shape[1]
+    Ad = torch.from_numpy(A).to("cuda:0").double()
+    Ud = torch.from_numpy(U).to("cuda:0").double()
+    G = Ud.t().contiguous() @ Ud
+    G.diagonal().sub_(1.0)
+    orth = torch.linalg.norm(G).item() / n ** 0.5
+    resid = (torch.linalg.norm(Ad - Ud @ torch.from_numpy(H).to("cuda:0").double()).item() /
+             torch.linalg.norm(Ad).item())
+    return orth, resid
+
+
+def serving_section(la, pool, rate=100.0, duration=30.0, seed=401, exclude_s=1.0,
+                    check_every=25):
     """Poisson stream of requests from the pool against the continuous-batching
     server; p50/p99 latency from submit to completed poll, over the requests
-    submitted after the first exclude_s seconds (warm-up of the queue)."""
+    submitted after the first exclude_s seconds (warm-up of the queue).  Only
+    requests that end with status OK count; every check_every-th result is
+    checked afterwards (FP64 orthogonality and residual <= 1e-5)."""
+    import torch
+
     import la_inputs
 
     stream = la_inputs.serve_stream(rate, duration, seed, len(pool))
     lat = []
     flops = 0.0
+    bad = 0
+    done = 0
+    samples = []
     with la.Server(16 << 30, max_slots=64) as srv:
         w = srv.submit(pool[0])            # touch the code paths once
         while srv.poll(w) is None:
@@ -365,31 +386,43 @@ def serving_section(la, pool, rate=100.0, duration=10.0, seed=401, exclude_s=1.0
                 A = pool[stream[i][1]]
                 t_sub = time.perf_counter()
                 rid = srv.submit(A)
-                pending[rid] = (t_sub, A.shape[0], stream[i][0] >= exclude_s)
+                pending[rid] = (t_sub, stream[i][1], stream[i][0] >= exclude_s)
                 i += 1
             for rid in list(pending):
-                r = srv.poll(rid, want_h=False)
+                sample = (done + 1) % check_every == 0
+                r = srv.poll(rid, want_h=sample)
                 if r is not None:
-                    t_sub, n, counted = pending.pop(rid)
+                    t_sub, pi, counted = pending.pop(rid)
+                    done += 1
+                    if r[0] != la.Status.OK:
+                        bad += 1
+                        continue
                     if counted:
                         lat.append(time.perf_counter() - t_sub)
                     k = r[3]["iters_precond"] + r[3]["iters_ns"]
-                    flops += (3.0 * k + 2.0) * float(n) ** 3
+                    flops += (3.0 * k + 2.0) * float(pool[pi].shape[0]) ** 3
+                    if sample:
+                        samples.append((pi, r[1], r[2]))
             time.sleep(0.0002)
         wall = time.perf_counter() - start
         st = srv.stats()
+    checks = [served_errors(torch, pool[pi], U, H) for pi, U, H in samples]
+    worst = max((max(o, r) for o, r in checks), default=float("nan"))
     lat_ms = np.array(lat) * 1e3
     out = {"workload": f"Poisson arrivals at {rate:g} req/s for {duration:g} s, square n "
                        f"log-uniform in [128, 4096] (x64), cond 10^U(1,6), pool of {len(pool)} "
                        f"(seed {seed}), AUTO policy; latency over arrivals after {exclude_s:g} s",
            "requests": int(len(stream)), "latency_samples": int(len(lat)),
+           "failed_requests": int(bad),
            "p50_ms": round(float(np.percentile(lat_ms, 50)), 2),
            "p99_ms": round(float(np.percentile(lat_ms, 99)), 2),
            "mean_ms": round(float(lat_ms.mean()), 2),
            "throughput_req_s": round(len(stream) / wall, 1),
            "tflops_algorithmic": round(flops / wall / 1e12, 2),
            "ticks": int(st["ticks"]), "gpu_busy_frac": round(st["busy_seconds"] / wall, 3),
-           "arena_high_water_gib": round(st["arena_high_water"] / 2 ** 30, 2)}
+           "arena_high_water_gib": round(st["arena_high_water"] / 2 ** 30, 2),
+           "checked_results": len(checks), "checked_worst_orth_or_resid": float(f"{worst:.3g}"),
+           "checked_all_within_1e-5": bool(checks) and worst <= 1e-5}
     print(f"[bench] serving {rate:g} req/s: {out}", file=sys.stderr, flush=True)
     return out
 
@@ -402,17 +435,21 @@ def serving_saturation(la, pool, count=160, seed=402):
     with la.Server(16 << 30, max_slots=64) as srv:
         start = time.perf_counter()
         pending = {srv.submit(pool[int(j)]): pool[int(j)].shape[0] for j in idx}
+        bad = 0
         while pending:
             for rid in list(pending):
                 r = srv.poll(rid, want_h=False)
                 if r is not None:
                     n = pending.pop(rid)
+                    if r[0] != la.Status.OK:
+                        bad += 1
+                        continue
                     k = r[3]["iters_precond"] + r[3]["iters_ns"]
                     flops += (3.0 * k + 2.0) * float(n) ** 3
             time.sleep(0.0005)
         wall = time.perf_counter() - start
-    out = {"requests": count, "seconds": round(wall, 2),
-           "throughput_req_s": round(count / wall, 1),
+    out = {"requests": count, "failed_requests": bad, "seconds": round(wall, 2),
+           "throughput_req_s": round((count - bad) / wall, 1),
            "tflops_algorithmic": round(flops / wall / 1e12, 1)}
     print(f"[bench] serving saturation: {out}", file=sys.stderr, flush=True)
     return out
@@ -432,7 +469,7 @@ def main():
     ap.add_argument("--serving-sweep", action="store_true",
                     help="also run the serving stream at 25/50/150/200 req/s and a saturation "
                          "burst (about 1.5 minutes more)")
-    ap.add_argument("--serving-seconds", type=float, default=10.0,
+    ap.add_argument("--serving-seconds", type=float, default=30.0,
                     help="length of the Poisson stream")
     ap.add_argument("--no-tall", action="store_true", help="skip the 131072 x 4096 polar")
     ap.add_argument("--no-oracle-polar", action="store_true")
@@ -482,8 +519,9 @@ def main():
         return
     if args.serving_only:
         pool = serving_pool(torch)
-        print(json.dumps({"serving": serving_section(la, pool, duration=args.serving_seconds)}),
-              flush=True)
+        res = serving_section(la, pool, duration=args.serving_seconds)
+        res["saturation"] = serving_saturation(la, pool)
+        print(json.dumps({"serving": res}), flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -609,11 +647,11 @@ def main():
     if not args.no_serving and args.only is None:
         pool = serving_pool(torch)
         out["serving"] = serving_section(la, pool, duration=args.serving_seconds)
+        out["serving"]["saturation"] = serving_saturation(la, pool)
         if args.serving_sweep:
             out["serving_sweep"] = {f"{r:g}": serving_section(la, pool, rate=r,
                                                               duration=args.serving_seconds)
                                     for r in (25.0, 50.0, 150.0, 200.0)}
-            out["serving_saturation"] = serving_saturation(la, pool)
     print(json.dumps(out), flush=True)
 
 

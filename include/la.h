@@ -148,7 +148,7 @@ la_status la_gemm_packed(la_context *ctx, int64_t m, int64_t n, int64_t k, float
 
 /* Options; a zero-initialised struct means the defaults in brackets. */
 typedef struct {
-    double s_minus;   /* threshold s_- of eq. (a_def)                   [0.1]   */
+    double s_minus;   /* threshold s_- of eq. (a_def), in [1e-3, 1)      [0.1]   */
     double s0;        /* estimate of the smallest singular value of
                          A / ||A||_F; fixes the preconditioning count     [2^-23] */
     double eps;       /* tolerance: stop once ||U' - U||_F <= max(M,N) eps [2^-23] */

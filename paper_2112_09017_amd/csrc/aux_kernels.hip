@@ -170,6 +170,19 @@ __global__ void scale_kernel(const float *__restrict__ X, int64_t ldx, float *__
             Y[r * ldy + c] = (float)((double)X[r * ldx + c] / nrm);
 }
 
+// scale_kernel with nrm = sqrt(*nrm2) taken on the device (FP64, correctly
+// rounded as on the host).
+__global__ void scale_by_norm_kernel(const float *__restrict__ X, int64_t ldx,
+                                     float *__restrict__ Y, int64_t ldy, int64_t m, int64_t n,
+                                     const double *__restrict__ nrm2)
+{
+    const double nrm = sqrt(*nrm2);
+    for (int64_t r = blockIdx.y; r < m; r += gridDim.y)
+        for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+             c += (int64_t)gridDim.x * blockDim.x)
+            Y[r * ldy + c] = (float)((double)X[r * ldx + c] / nrm);
+}
+
 // X = A^T / a for an n x m A (X is m x n): 32 x 32 tiles staged through LDS
 // (padded rows) so that both the read of A and the write of X are coalesced.
 // The division is done in FP64 and rounded once, as in scale_kernel.
@@ -238,38 +251,96 @@ __global__ void symmetrize_kernel(float *H, int64_t ldh, int64_t n)
 // adds the 64 x 64 tile (bi, bj) of the slices in FP64 in slice order,
 // applies the epilogue in FP64, rounds once, writes the tile and, through
 // LDS, its transpose at (bj, bi), so out is exactly symmetric and both
-// writes are coalesced.
+// writes are coalesced.  VEC (n, ldo and the slice stride multiples of 4,
+// 16-byte aligned bases): each thread moves 4 x 4 elements as float4 rows.
 constexpr int kSymTile = 64;
 
+template <bool VEC>
 __global__ void __launch_bounds__(256) splitk_sym_reduce_kernel(
-    const float *__restrict__ parts, int splits, int64_t n, double alpha, double gamma,
-    float *__restrict__ out, int64_t ldo)
+    const float *__restrict__ parts, int64_t stride, int splits, int64_t n, double alpha,
+    double gamma, float *__restrict__ out, int64_t ldo)
 {
     const int64_t bi = blockIdx.y, bj = blockIdx.x;
     if (bj < bi)
         return;
     __shared__ float t[kSymTile][kSymTile + 1];
-    const int64_t nn = n * n;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int r = ty; r < kSymTile; r += 4) {
-        const int64_t i = bi * kSymTile + r, j = bj * kSymTile + tx;
-        if (i < n && j < n && i <= j) {
-            double acc = 0.0;
-            for (int s = 0; s < splits; ++s)
-                acc += (double)parts[s * nn + i * n + j];
-            double v = alpha * acc;
-            if (i == j)
-                v += gamma;
-            const float f = (float)v;
-            out[i * ldo + j] = f;
-            t[r][tx] = f;
+    const bool diag = bi == bj;
+    if constexpr (VEC) {
+        const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;   // float4 column, row phase
+        const int64_t j0 = bj * kSymTile + 4 * tx;
+        for (int r = ty; r < kSymTile; r += 16) {
+            const int64_t i = bi * kSymTile + r;
+            if (i >= n || j0 >= n)
+                continue;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int sl = 0; sl < splits; ++sl) {
+                const float4 v =
+                    *reinterpret_cast<const float4 *>(parts + sl * stride + i * n + j0);
+                acc[0] += (double)v.x;
+                acc[1] += (double)v.y;
+                acc[2] += (double)v.z;
+                acc[3] += (double)v.w;
+            }
+            float f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double v = alpha * acc[q];
+                if (i == j0 + q)
+                    v += gamma;
+                f[q] = (float)v;
+                t[r][4 * tx + q] = f[q];
+            }
+            if (!diag) {
+                *reinterpret_cast<float4 *>(out + i * ldo + j0) = make_float4(f[0], f[1], f[2], f[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i <= j0 + q)
+                        out[i * ldo + j0 + q] = f[q];
+            }
         }
-    }
-    __syncthreads();
-    for (int r = ty; r < kSymTile; r += 4) {
-        const int64_t j = bj * kSymTile + r, i = bi * kSymTile + tx;   // out(j, i), i < j
-        if (i < n && j < n && i < j)
-            out[j * ldo + i] = t[tx][r];
+        __syncthreads();
+        // out(j, i) for i < j: row j of the (bj, bi) tile, columns i0 .. i0 + 3
+        const int64_t i0 = bi * kSymTile + 4 * tx;
+        for (int r = ty; r < kSymTile; r += 16) {
+            const int64_t j = bj * kSymTile + r;
+            if (j >= n || i0 >= n)
+                continue;
+            float f[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                f[q] = t[4 * tx + q][r];
+            if (!diag) {
+                *reinterpret_cast<float4 *>(out + j * ldo + i0) = make_float4(f[0], f[1], f[2], f[3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + q < j)
+                        out[j * ldo + i0 + q] = f[q];
+            }
+        }
+    } else {
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+        for (int r = ty; r < kSymTile; r += 4) {
+            const int64_t i = bi * kSymTile + r, j = bj * kSymTile + tx;
+            if (i < n && j < n && i <= j) {
+                double acc = 0.0;
+                for (int sl = 0; sl < splits; ++sl)
+                    acc += (double)parts[sl * stride + i * n + j];
+                double v = alpha * acc;
+                if (i == j)
+                    v += gamma;
+                const float f = (float)v;
+                out[i * ldo + j] = f;
+                t[r][tx] = f;
+            }
+        }
+        __syncthreads();
+        for (int r = ty; r < kSymTile; r += 4) {
+            const int64_t j = bj * kSymTile + r, i = bi * kSymTile + tx;   // out(j, i), i < j
+            if (i < n && j < n && i < j)
+                out[j * ldo + i] = t[tx][r];
+        }
     }
 }
 
@@ -277,6 +348,9 @@ __global__ void __launch_bounds__(256) splitk_sym_reduce_kernel(
 // m x n row-major (ld n), with the FP64 partial sum of (out - E)^2 of block b
 // in step[b] (step may be null).  Every thread visits its elements in a fixed
 // order and the block sum is a fixed tree, so the partials are reproducible.
+// VEC (n, lde, ldo multiples of 4, 16-byte aligned bases): four consecutive
+// columns per thread and step, as float4 loads and stores.
+template <bool VEC>
 __global__ void __launch_bounds__(kThreads) splitk_update_reduce_kernel(
     const float *__restrict__ parts, int splits, int64_t m, int64_t n, double alpha, double beta,
     const float *__restrict__ E, int64_t lde, float *__restrict__ out, int64_t ldo,
@@ -285,17 +359,43 @@ __global__ void __launch_bounds__(kThreads) splitk_update_reduce_kernel(
     __shared__ double sh[kThreads / 64];
     const int64_t mn = m * n;
     double ss = 0.0;
-    for (int64_t r = blockIdx.x; r < m; r += gridDim.x)
-        for (int64_t c = threadIdx.x; c < n; c += kThreads) {
-            double acc = 0.0;
-            for (int s = 0; s < splits; ++s)
-                acc += (double)parts[s * mn + r * n + c];
-            const double e = E ? (double)E[r * lde + c] : 0.0;
-            const float v = (float)(alpha * acc + beta * e);
-            out[r * ldo + c] = v;
-            const double df = (double)v - e;
-            ss += df * df;
-        }
+    if constexpr (VEC) {
+        for (int64_t r = blockIdx.x; r < m; r += gridDim.x)
+            for (int64_t c = 4 * (int64_t)threadIdx.x; c < n; c += 4 * kThreads) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int sl = 0; sl < splits; ++sl) {
+                    const float4 v = *reinterpret_cast<const float4 *>(parts + sl * mn + r * n + c);
+                    acc[0] += (double)v.x;
+                    acc[1] += (double)v.y;
+                    acc[2] += (double)v.z;
+                    acc[3] += (double)v.w;
+                }
+                float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (E)
+                    e = *reinterpret_cast<const float4 *>(E + r * lde + c);
+                const double ev[4] = {(double)e.x, (double)e.y, (double)e.z, (double)e.w};
+                float o[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    o[q] = (float)(alpha * acc[q] + beta * ev[q]);
+                    const double df = (double)o[q] - ev[q];
+                    ss += df * df;
+                }
+                *reinterpret_cast<float4 *>(out + r * ldo + c) = make_float4(o[0], o[1], o[2], o[3]);
+            }
+    } else {
+        for (int64_t r = blockIdx.x; r < m; r += gridDim.x)
+            for (int64_t c = threadIdx.x; c < n; c += kThreads) {
+                double acc = 0.0;
+                for (int sl = 0; sl < splits; ++sl)
+                    acc += (double)parts[sl * mn + r * n + c];
+                const double e = E ? (double)E[r * lde + c] : 0.0;
+                const float v = (float)(alpha * acc + beta * e);
+                out[r * ldo + c] = v;
+                const double df = (double)v - e;
+                ss += df * df;
+            }
+    }
     if (step) {
         const double t = block_sum(ss, sh);
         if (threadIdx.x == 0)
@@ -350,6 +450,16 @@ hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy, int6
     return hipGetLastError();
 }
 
+hipError_t launch_scale_by_norm(const float *X, int64_t ldx, float *Y, int64_t ldy, int64_t m,
+                                int64_t n, const double *nrm2, hipStream_t s)
+{
+    if (m == 0 || n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(scale_by_norm_kernel, grid2d(m, n), dim3(kThreads), 0, s, X, ldx, Y, ldy,
+                       m, n, nrm2);
+    return hipGetLastError();
+}
+
 hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t ldx, int64_t n,
                                   int64_t m, double a, hipStream_t s)
 {
@@ -401,21 +511,34 @@ hipError_t launch_splitk_update_reduce(const float *parts, int splits, int64_t m
 {
     if (m == 0 || n == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(splitk_update_reduce_kernel, dim3(kSumsqBlocks), dim3(kThreads), 0, s,
-                       parts, splits, m, n, alpha, beta, E, lde, out, ldo, step);
+    const bool vec = n % 4 == 0 && aligned16(parts) && aligned16(out) && ldo % 4 == 0 &&
+                     (!E || (aligned16(E) && lde % 4 == 0));
+    if (vec)
+        hipLaunchKernelGGL(splitk_update_reduce_kernel<true>, dim3(kSumsqBlocks), dim3(kThreads),
+                           0, s, parts, splits, m, n, alpha, beta, E, lde, out, ldo, step);
+    else
+        hipLaunchKernelGGL(splitk_update_reduce_kernel<false>, dim3(kSumsqBlocks), dim3(kThreads),
+                           0, s, parts, splits, m, n, alpha, beta, E, lde, out, ldo, step);
     return hipGetLastError();
 }
 
-hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n, double alpha,
-                                    double gamma, float *out, int64_t ldo, hipStream_t s)
+hipError_t launch_splitk_sym_reduce(const float *parts, int64_t stride, int splits, int64_t n,
+                                    double alpha, double gamma, float *out, int64_t ldo,
+                                    hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
     const int64_t nb = (n + kSymTile - 1) / kSymTile;
     if (nb > 65535)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(splitk_sym_reduce_kernel, dim3((unsigned)nb, (unsigned)nb), dim3(256), 0, s,
-                       parts, splits, n, alpha, gamma, out, ldo);
+    const bool vec = n % 4 == 0 && stride % 4 == 0 && ldo % 4 == 0 && aligned16(parts) &&
+                     aligned16(out);
+    if (vec)
+        hipLaunchKernelGGL(splitk_sym_reduce_kernel<true>, dim3((unsigned)nb, (unsigned)nb),
+                           dim3(256), 0, s, parts, stride, splits, n, alpha, gamma, out, ldo);
+    else
+        hipLaunchKernelGGL(splitk_sym_reduce_kernel<false>, dim3((unsigned)nb, (unsigned)nb),
+                           dim3(256), 0, s, parts, stride, splits, n, alpha, gamma, out, ldo);
     return hipGetLastError();
 }
 

@@ -98,69 +98,8 @@ bool valid_prec(int p)
 
 // ------------------------------------------------------------------ polar plan
 
-// FP32 accumulation depth.  Every product accumulates in FP32 on the matrix
-// cores, one rounding per MFMA, so the rounding error of an output grows with
-// the number of accumulation steps along K; inside the preconditioning steps
-// it is amplified (the polynomial's relative condition near sigma = 1 is about
-// 23 at s_- = 0.1).  The iteration's products with K above kMaxAccK are
-// therefore split along K into slices of at most kMaxAccK, each accumulated in
-// FP32, and the slices are added in FP64 in slice order and rounded once.
-// (la_polar_opts.max_acc_k overrides the depth.)
-constexpr int64_t kMaxAccK = 4096;
-
-
-la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts, PolarPlan *out)
-{
-    la_polar_opts o;
-    memset(&o, 0, sizeof o);
-    if (opts)
-        o = *opts;
-    if (m < 1 || n < 1 || m < n) {
-        set_error("polar needs m >= n >= 1 (got m=%lld n=%lld)", (long long)m, (long long)n);
-        return LA_ERR_SHAPE;
-    }
-    if (!valid_prec(o.prec_precond) || !valid_prec(o.prec_ns) || !valid_prec(o.prec_h)) {
-        set_error("invalid la_precision in la_polar_opts");
-        return LA_ERR_INVALID_ARG;
-    }
-    PolarPlan p;
-    p.m = m;
-    p.n = n;
-    p.s_minus = o.s_minus > 0 ? o.s_minus : 0.1;
-    p.s0 = o.s0 > 0 ? o.s0 : ldexp(1.0, -23);
-    p.eps = o.eps > 0 ? o.eps : ldexp(1.0, -23);
-    p.max_iter = o.max_iter > 0 ? o.max_iter : 100;
-    p.polish = o.polish != 0;
-    if (o.max_acc_k < 0) {
-        set_error("la_polar_opts: max_acc_k must be >= 0");
-        return LA_ERR_INVALID_ARG;
-    }
-    p.max_acc = o.max_acc_k > 0 ? ((int64_t)o.max_acc_k + 31) / 32 * 32 : kMaxAccK;
-    p.stagnation = o.no_stagnation == 0;
-    if (!(p.s_minus < 1.0) || !isfinite(p.s0) || !isfinite(p.eps)) {
-        set_error("la_polar_opts: need 0 < s_minus < 1 and finite s0, eps");
-        return LA_ERR_INVALID_ARG;
-    }
-    p.prec_pre = resolve_prec(o.prec_precond, PREC_BF16X6);
-    p.prec_ns = resolve_prec(o.prec_ns, PREC_BF16X3);
-    // H = sym(U^T A) is one product (about 2 of the ~85 N^3 of a polar) but its
-    // error enters the residual directly: at 3xBF16 it alone is about
-    // 2^-16 ||A||_F, so AUTO computes it at 6xBF16.
-    p.prec_h = resolve_prec(o.prec_h, PREC_BF16X6);
-    // eq. (a_def) and the recurrence of eq. (RogueScalar): the number of
-    // preconditioning steps is fixed before any matrix work.
-    p.a = 1.5 * sqrt(3.0) - p.s_minus;
-    p.c = (4.0 / 27.0) * p.a * p.a;
-    double s = p.s0;
-    int k = 0;
-    while (s < p.s_minus && k < 1000) {
-        s = p.a * s * (1.0 - p.c * s * s);
-        ++k;
-    }
-    p.k_pre = k;
-    *out = p;
-    return LA_OK;
-}
+// (polar_plan, the FP32 accumulation depth kMaxAccK and the stop test are in
+// polar_host.h)
 
 int acc_splits(int64_t K, int64_t max_acc)
 {
@@ -412,7 +351,7 @@ static hipError_t gram_step(const PolarPlan &p, int prec, const float *X, int64_
     hipError_t e = gram_slices(prec, X, ldx, X, ldx, m, n, splits, w.parts, &count, s);
     if (e != hipSuccess)
         return e;
-    return launch_splitk_sym_reduce(w.parts, count, n, alpha, gamma, P, n, s);
+    return launch_splitk_sym_reduce(w.parts, n * n, count, n, alpha, gamma, P, n, s);
 }
 
 // Xn <- alpha X P + beta X (partials of (Xn - X)^2 in tiles if tiles != null;
@@ -481,7 +420,7 @@ static hipError_t h_step(const PolarPlan &p, const float *U, int64_t ldu, const 
     e = gram_slices(p.prec_h, A, lda, U, ldu, p.m, n, want, w.parts + (size_t)c1 * n * n, &c2, s);
     if (e != hipSuccess)
         return e;
-    return launch_splitk_sym_reduce(w.parts, c1 + c2, n, 0.5, 0.0, H, ldh, s);
+    return launch_splitk_sym_reduce(w.parts, n * n, c1 + c2, n, 0.5, 0.0, H, ldh, s);
 }
 
 // ------------------------------------------------------------------ inverse
@@ -1133,14 +1072,12 @@ static la_status polar_impl(la_context *ctx, const PolarPlan &p, const float *A,
         inf.iters_precond++;
     }
 
-    // Newton-Schulz: U' = U + U (I - U^T U) / 2, delta = ||U' - U||_F
-    const double tol = (double)std::max(m, n) * p.eps;
-    double prev = INFINITY;
-    const int total = p.max_iter + (p.polish ? 1 : 0);
-    bool stopped = false;
-    for (int it = 0; it < total; ++it) {
-        const bool polishing = stopped;
-        const int prec = polishing ? PREC_BF16X6 : p.prec_ns;
+    // Newton-Schulz: U' = U + U (I - U^T U) / 2, delta = ||U' - U||_F, until the
+    // stop test (polar_host.h); a polish step runs at BF16X6
+    StopState stop;
+    bool converged = false;
+    for (;;) {
+        const int prec = stop.stopped ? PREC_BF16X6 : p.prec_ns;
         int ntiles = 0;
         LA_HIP(gram_step(p, prec, buf[cur], ld[cur], -1.0, 1.0, w.P, w, s),
                "la_polar: NS gram");
@@ -1161,19 +1098,13 @@ static la_status polar_impl(la_context *ctx, const PolarPlan &p, const float *A,
             set_error("la_polar: step norm is not finite");
             return LA_ERR_NONFINITE;
         }
-        if (polishing)
+        const StopDecision d = stop_test(p, m, n, delta, stop, inf.iters_ns);
+        inf.stop_reason = stop.reason;
+        if (d == STOP_DONE) {
+            converged = true;
             break;
-        if (delta <= tol) {
-            inf.stop_reason = 0;
-            stopped = true;
-        } else if (p.stagnation && delta < 1e-2 * sqrt((double)n) && delta > 0.5 * prev) {
-            inf.stop_reason = 1;
-            stopped = true;
         }
-        prev = delta;
-        if (stopped && !p.polish)
-            break;
-        if (!stopped && it + 1 >= p.max_iter)
+        if (d == STOP_CAP)
             break;
     }
     if (cur != 0)
@@ -1184,7 +1115,7 @@ static la_status polar_impl(la_context *ctx, const PolarPlan &p, const float *A,
     LA_HIP(hipStreamSynchronize(s), "la_polar: final sync");
     if (info)
         *info = inf;
-    if (!stopped) {
+    if (!converged) {
         set_error("la_polar: no convergence after %d Newton-Schulz steps (delta %g)",
                   inf.iters_ns, inf.last_delta);
         return LA_ERR_NOT_CONVERGED;

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/la.h"
+#include "polar_host.h"
 
 struct la_context {
     int device;
@@ -15,9 +16,6 @@ struct la_context {
 };
 
 namespace la {
-
-// Resolved product arithmetic (la_precision without AUTO).
-enum Prec : int { PREC_FP32 = 1, PREC_BF16X3 = 2, PREC_BF16X6 = 3 };
 
 // One GEMM-shaped launch: out = alpha * op(A) op(B) + beta * E + gamma * I.
 //   op(A) (M x K): a_kcontig ? A[i * lda + k] : A[k * lda + i]
@@ -99,6 +97,9 @@ hipError_t launch_reduce_fixed(const double *parts, int64_t count, double *out,
 // power of two leaves Y bitwise unchanged).
 hipError_t launch_scale(const float *X, int64_t ldx, float *Y, int64_t ldy,
                         int64_t m, int64_t n, double nrm, hipStream_t s);
+// The same with nrm = sqrt(*nrm2) read on the device (no host round trip).
+hipError_t launch_scale_by_norm(const float *X, int64_t ldx, float *Y, int64_t ldy,
+                                int64_t m, int64_t n, const double *nrm2, hipStream_t s);
 // X = A^T / a (FP64 division, rounded once); A is n x m, X is m x n.
 hipError_t launch_transpose_scale(const float *A, int64_t lda, float *X, int64_t ldx,
                                   int64_t n, int64_t m, double a, hipStream_t s);
@@ -114,7 +115,9 @@ hipError_t launch_symmetrize(float *H, int64_t ldh, int64_t n, hipStream_t s);
 // alpha * sum_s part_s(i, j) + gamma * [i == j], summed over s in order in
 // FP64 and rounded once; parts are `splits` exactly symmetric n x n slices
 // (row-major, ld n).
-hipError_t launch_splitk_sym_reduce(const float *parts, int splits, int64_t n,
+// Slice s is at parts + s * stride (elements; any distance within one
+// allocation).
+hipError_t launch_splitk_sym_reduce(const float *parts, int64_t stride, int splits, int64_t n,
                                     double alpha, double gamma, float *out,
                                     int64_t ldo, hipStream_t s);
 // Split-K reduction of an m x n product: out = alpha * sum_s part_s + beta * E
@@ -135,24 +138,14 @@ struct ReduceItem {
 };
 hipError_t launch_reduce_grouped(const ReduceItem *items_dev, int n, hipStream_t s);
 
-// Polar building blocks shared by la_polar and the server.
-struct PolarPlan {
-    int64_t m, n;
-    double s_minus, s0, eps, a, c;
-    int k_pre, max_iter, polish, stagnation;
-    int64_t max_acc;   // FP32 accumulation depth of the split-K products
-    int prec_pre, prec_ns, prec_h;
-};
-la_status polar_plan(int64_t m, int64_t n, const la_polar_opts *opts,
-                     PolarPlan *out);
+// Polar building blocks shared by la_polar and the server (PolarPlan,
+// polar_plan and the stop test are in polar_host.h).
 // Number of split-K slices the Gram of an m x n iterate uses, and the number
 // needed to keep an inner dimension K within the FP32 accumulation depth.
 int gram_splits(int64_t m, int64_t n, int prec, int64_t max_acc);
 int acc_splits(int64_t K, int64_t max_acc);
 size_t polar_workspace_bytes(const PolarPlan &p);
 
-// Thread-local error text.
-void set_error(const char *fmt, ...);
 
 // Argument helpers shared by the ABI entry points (la_api.hip).
 la_status dev_fail(hipError_t e, const char *where);   // sets the error, LA_ERR_DEVICE

@@ -83,6 +83,57 @@ def test_mix_equals_alone_and_meets_tolerance(la):
         assert orth <= TOL and resid <= TOL and dh <= TOL
 
 
+def fp64_checks(A32, U, H, V, s):
+    """Exact FP64 orthogonality, residual and ||H - V diag(s) V^T||_F / ||A||_F
+    by torch products on the GPU (test tooling)."""
+    import torch
+    n = U.shape[1]
+    Ad = torch.from_numpy(A32).to("cuda").double()
+    Ud = torch.from_numpy(U).to("cuda").double()
+    Hd = torch.from_numpy(H).to("cuda").double()
+    G = Ud.t().contiguous() @ Ud
+    G.diagonal().sub_(1.0)
+    orth = torch.linalg.norm(G).item() / math.sqrt(n)
+    nA = torch.linalg.norm(Ad).item()
+    resid = torch.linalg.norm(Ad - Ud @ Hd).item() / nA
+    sd = torch.from_numpy(s).to("cuda")
+    dh = torch.linalg.norm(Hd - (V * sd[None, :]) @ V.t().contiguous()).item() / nA
+    return orth, resid, dh
+
+
+def test_large_tile_requests_mix_equals_alone(la):
+    """N = 3072 and N = 4096 requests (cond 1e6 and 1e5) take the grouped
+    kernels' 256 x 256 tiles (updates of both, the 4096 Grams too, at 6xBF16
+    and 3xBF16); served among small requests they are bitwise the same as
+    served alone, and meet the tolerances by exact FP64 checks."""
+    import torch
+    big = []
+    for n, lo, seeds in ((3072, 1e-6, (990, 991, 992)), (4096, 1e-5, (993, 994, 995))):
+        A, Q, s, V = la_inputs.polar_case_torch(n, n, lo, seeds)
+        del Q
+        big.append((A, s, V))
+    torch.cuda.empty_cache()
+    small = cases()[:4]
+    with la.Server(8 << 30, max_slots=16) as srv:
+        ids = [srv.submit(small[0].A32), srv.submit(big[0][0]), srv.submit(small[1].A32),
+               srv.submit(big[1][0]), srv.submit(small[2].A32), srv.submit(small[3].A32)]
+        mix = wait_all(srv, ids, timeout=300)
+        st = srv.stats()
+    assert st["completed"] == len(ids)
+    for (A, s, V), i in zip(big, (ids[1], ids[3])):
+        status, U, H, info = mix[i]
+        assert status == la.Status.OK
+        with la.Server(8 << 30) as alone:
+            j = alone.submit(A)
+            s2, U2, H2, info2 = wait_all(alone, [j], timeout=300)[j]
+        assert np.array_equal(U, U2) and np.array_equal(H, H2), A.shape
+        assert info == info2
+        assert np.array_equal(H, H.T)
+        orth, resid, dh = fp64_checks(A, U, H, V, s)
+        print(A.shape, info, f"orth={orth:.2e} resid={resid:.2e} dH={dh:.2e}")
+        assert orth <= TOL and resid <= TOL and dh <= TOL
+
+
 def test_tight_arena_admission(la):
     """An arena that holds two 512 x 512 requests at a time still serves six."""
     cs = [la_inputs.polar_case(512, 512, 1e-3, seeds=(930 + i, 940 + i, 950 + i))
