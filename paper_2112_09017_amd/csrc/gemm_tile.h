@@ -43,6 +43,11 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.
 constexpr int kXcds = 8;
 
+// s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
+// vmcnt bits [3:0] and [15:14] zero, expcnt [6:4] and lgkmcnt [11:8] at their
+// maxima (no wait).
+constexpr int kWaitVmcnt0 = (7 << 4) | (15 << 8);
+
 // ---------------------------------------------------------------- configs
 
 // A kernel's PREC template argument is the arithmetic (PREC_FP32 / _BF16X3 /
@@ -670,6 +675,13 @@ __device__ __forceinline__ void round_tile_coords(const GemmDesc &d, int &tm, in
     }
 }
 
+// Epilogue of one tile: out = alpha acc + beta E + gamma I, written to C (and
+// mirrored for a full Gram), with the FP64 sum of (out - E)^2 for the step
+// norm.  Each 32 x 32 block's 16 addend values per lane are loaded together,
+// before any of the block's stores (C may alias E, so a load placed after a
+// store would have to wait for it), and one explicit wait for them follows:
+// without it the per-element bounds branches make the compiler wait for every
+// outstanding memory operation, stores included, before each element.
 template <int PREC>
 __device__ __forceinline__ void epilogue(const GemmDesc &d,
                                          f32x16 (&acc)[Geo<PREC>::FM][Geo<PREC>::FN],
@@ -684,18 +696,30 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
 #pragma clang loop unroll(full)
     for (int i = 0; i < G::FM; ++i)
 #pragma clang loop unroll(full)
-        for (int j = 0; j < G::FN; ++j)
+        for (int j = 0; j < G::FN; ++j) {
+            const int64_t col = cb + j * 32;
+            float ev[16];
+            if (d.E) {
+                // past the edge a clamped in-range element is read and not used
+                const int64_t cc = col < d.N ? col : d.N - 1;
+#pragma clang loop unroll(full)
+                for (int e = 0; e < 16; ++e) {
+                    int64_t row = rb + i * 32 + (e >> 2) * 8 + (e & 3);
+                    row = row < d.M ? row : d.M - 1;
+                    ev[e] = d.E[row * d.lde + cc];
+                }
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+            }
 #pragma clang loop unroll(full)
             for (int e = 0; e < 16; ++e) {
                 const int64_t row = rb + i * 32 + (e >> 2) * 8 + (e & 3);
-                const int64_t col = cb + j * 32;
                 if (row >= d.M || col >= d.N || (d.gram && row > col))
                     continue;
                 float val = d.alpha * acc[i][j][e];
-                float ev = 0.0f;
+                float evv = 0.0f;
                 if (d.E) {
-                    ev = d.E[row * d.lde + col];
-                    val = val + d.beta * ev;
+                    evv = ev[e];
+                    val = val + d.beta * evv;
                 }
                 if (row == col)
                     val = val + d.gamma;
@@ -703,10 +727,11 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
                 if (d.gram && !d.gram_upper && row != col)
                     d.C[col * d.ldc + row] = val;
                 if (want_ss) {
-                    const double df = (double)val - (double)ev;
+                    const double df = (double)val - (double)evv;
                     ss += df * df;
                 }
             }
+        }
     if (want_ss) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)

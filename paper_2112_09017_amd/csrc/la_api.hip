@@ -205,9 +205,24 @@ static hipError_t gemm_packed_or_plain(int prec, GemmDesc d, char *pk, hipStream
     return launch_gemm(prec, d, s);
 }
 
+// Whether a Gram X^T X (n x n, K = m) at prec runs on the packed-operand
+// kernel: 3xBF16 with at least 128 upper 256 x 256 tiles and K >= 256.  X^T is
+// packed once and serves as both operands.
+static bool gram_packs(int prec, int64_t m, int64_t n)
+{
+    const int64_t nb = (n + 255) / 256;
+    return prec == PREC_BF16X3 && m >= 256 && nb * (nb + 1) / 2 >= 128;
+}
+
+// Packed copies the iteration keeps: X and P for a packed update, or X^T for
+// a packed Gram (the Gram's pack is consumed before the update packs).
 static size_t packed_update_bytes(const PolarPlan &p)
 {
-    return std::max(pack_bytes(p.prec_pre, p.m, p.n, p.n), pack_bytes(p.prec_ns, p.m, p.n, p.n));
+    size_t b = std::max(pack_bytes(p.prec_pre, p.m, p.n, p.n), pack_bytes(p.prec_ns, p.m, p.n, p.n));
+    for (int pr : {p.prec_pre, p.prec_ns})
+        if (gram_packs(pr, p.m, p.n))
+            b = std::max(b, align_up256(packed_x3_bytes(p.n, p.m)));
+    return b;
 }
 
 // Slices of the update X P (K = n) and of each half of H (K = m).
@@ -292,7 +307,7 @@ static PolarWs carve(const PolarPlan &p, void *ws)
 // parts + y n^2.  *count receives the number of slices.
 static hipError_t gram_slices(int prec, const float *X1, int64_t ld1, const float *X2,
                               int64_t ld2, int64_t K, int64_t n, int want, float *parts,
-                              int *count, hipStream_t s)
+                              int *count, hipStream_t s, char *pk = nullptr)
 {
     GemmDesc d;
     memset(&d, 0, sizeof d);
@@ -314,6 +329,16 @@ static hipError_t gram_slices(int prec, const float *X1, int64_t ld1, const floa
     d.slices = slice_plan(K, want, &d.slice_k);
     d.slice_stride = n * n;
     *count = d.slices;
+    if (pk && X1 == X2 && ld1 == ld2 && gram_packs(prec, K, n) && !d.small) {
+        // X^T (n rows, K) packed once and read as both operands; the packed
+        // kernel computes every product exactly as the unpacked one
+        hipError_t e = launch_pack_x3(X1, ld1, 0, n, K, pk, s);
+        if (e != hipSuccess)
+            return e;
+        d.A = (const float *)pk;
+        d.B = (const float *)pk;
+        return launch_gemm_packed_x3(d, s);
+    }
     return launch_gemm(prec, d, s);
 }
 
@@ -348,7 +373,7 @@ static hipError_t gram_step(const PolarPlan &p, int prec, const float *X, int64_
     // the upper triangle of its own n x n part, and the parts are added in
     // slice order in FP64
     int count = 0;
-    hipError_t e = gram_slices(prec, X, ldx, X, ldx, m, n, splits, w.parts, &count, s);
+    hipError_t e = gram_slices(prec, X, ldx, X, ldx, m, n, splits, w.parts, &count, s, w.pk);
     if (e != hipSuccess)
         return e;
     return launch_splitk_sym_reduce(w.parts, n * n, count, n, alpha, gamma, P, n, s);

@@ -199,7 +199,9 @@ def test_workspace_sizes_follow_the_slice_and_pack_policies(L):
     # CUs); H takes 32 slices of U^T A and 32 of A^T U: 64 n x n parts
     base = 4 * (m * n + n * n + 64 * n * n)
     assert base <= fp32_ns < base + MiB
-    packed = L.la_pack_size(m, n) + L.la_pack_size(n, n)
+    # packed copies: X and P for the update, or X^T for the Gram (136 upper
+    # tiles), whichever is larger
+    packed = max(L.la_pack_size(m, n) + L.la_pack_size(n, n), L.la_pack_size(n, m))
     assert base + packed <= auto < base + packed + MiB
     # a deeper accumulation: 16 Gram slices (still at least the 15 that fill
     # the CUs) and 2 x 16 for H
