@@ -32,6 +32,7 @@ M, N, K = 16384, 16384, 32768
 PEAK_BF16 = 2516.6      # TFLOP/s, dense BF16 MFMA, MI355X
 PEAK_FP32 = 157.3       # TFLOP/s, FP32 MFMA, MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_packed_bf16x3_16384x16384x32768_traffic.json")
+MFMA_FILE = os.path.join(ROOT, "profiles", "gemm_packed_bf16x3_16384x16384x32768_mfma.json")
 KERNEL_SOURCES = ["paper_2112_09017_amd/csrc/gemm_tile.h", "paper_2112_09017_amd/csrc/gemm_x3.hip"]
 
 
@@ -54,6 +55,20 @@ def load_traffic():
     if t.get("kernel_hash") != kernel_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def load_mfma():
+    """Matrix-core busy fraction and clock of the packed kernel from the
+    committed rocprofv3 counter summary, or None if the kernel source changed
+    since the counters were taken."""
+    try:
+        with open(MFMA_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return {k: t[k] for k in ("mfma_busy", "clock_ghz", "bf16_mfma_tflops", "source") if k in t}
 
 
 def time_launches(fn, steps, warmup, torch):
@@ -610,6 +625,7 @@ def main():
             "frac": round(kernel_tflops / ceiling, 4),
             "kernel_ms": round(kernel_ms, 3) if kernel_ms else round(ms, 3),
             "traffic": traffic,
+            "mfma_util": load_mfma() if head == "BF16X3" else None,
             "peak_basis": ("BF16 dense MFMA 2516.6 TFLOP/s / 3 BF16 products per FP32-accurate "
                            "multiply-add" if head == "BF16X3" else
                            "BF16 dense MFMA / 6" if head == "BF16X6" else "FP32 MFMA 157.3"),

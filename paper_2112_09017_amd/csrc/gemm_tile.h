@@ -83,10 +83,11 @@ template <> struct Cfg<PREC_BF16X3 | kSmall> {
     static constexpr int terms = 2, entry_bytes = 16;
 };
 template <> struct Cfg<PREC_BF16X6 | kSmall> {
-    // two register stages of three terms do not fit two workgroups per CU.  The
-    // grouped kernel (one register stage) runs two per CU: its work-lists are
-    // long enough that the other workgroup's MFMAs cover this one's split.
-    static constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 2, GOCC = 2;
+    // two register stages of three terms fit within the 256 registers of two
+    // workgroups per CU (at most 212 used), so one workgroup's loads and split
+    // overlap the other's MFMAs; the grouped kernel (one register stage) runs two
+    // per CU too
+    static constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, OCC = 2, PIPE = 2, GOCC = 2;
     static constexpr int terms = 3, entry_bytes = 16;
 };
 
@@ -100,6 +101,15 @@ template <> struct Cfg<PREC_BF16X3 | kPacked> {
     static constexpr int BM = 256, BN = 256, BK = 16, WM = 2, WN = 2, OCC = 1, PIPE = 0, GOCC = 1;
     static constexpr int terms = 2, entry_bytes = 16;
 };
+
+// Workgroups per CU a kernel is compiled for: the tile class's OCC, except
+// that the small 6xBF16 tile with both operands k-major (its loader keeps a
+// 64-bit address per row it loads) would spill at two and keeps one.
+template <int PREC, bool AKC, bool BKC>
+constexpr int kernel_occ()
+{
+    return (PREC == (PREC_BF16X6 | kSmall) && !AKC && !BKC) ? 1 : Cfg<PREC>::OCC;
+}
 
 template <int PREC> struct Geo {
     using C = Cfg<PREC>;
@@ -1009,7 +1019,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &d, int tm, int tn, cha
 // ---------------------------------------------------------------- kernels
 
 template <int PREC, bool AKC, bool BKC>
-__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(GemmDesc d)
+__global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>())) gemm_kernel(GemmDesc d)
 {
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
@@ -1037,7 +1047,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_kernel(Gem
 // slice but the last is made of whole stages and keeps the operands' 16-byte
 // alignment.
 template <int PREC, bool AKC, bool BKC>
-__global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::OCC) gemm_sliced_kernel(GemmDesc d)
+__global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>()))
+    gemm_sliced_kernel(GemmDesc d)
 {
     __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
