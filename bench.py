@@ -442,7 +442,7 @@ def serving_section(la, pool, rate=100.0, duration=30.0, seed=401, exclude_s=1.0
     return out
 
 
-def serving_saturation(la, pool, count=160, seed=402):
+def serving_saturation(la, pool, count=480, seed=402):
     """All `count` requests submitted at once: completion throughput."""
     g = np.random.default_rng(seed)
     idx = g.integers(0, len(pool), size=count)
