@@ -143,14 +143,22 @@ def polar_errors(torch, Ad, U, H, V, sd):
             "h_err": float(f"{dh:.3g}")}
 
 
-def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
+def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303),
+                  counter_run=False):
     """Polar factorisation of an m x n A = Q diag(s) V^T (cond 1/lo), AUTO policy
-    (6xBF16 preconditioning and H, 3xBF16 Newton-Schulz) and all-FP32-MFMA."""
+    (6xBF16 preconditioning and H, 3xBF16 Newton-Schulz) and all-FP32-MFMA.
+    counter_run: build the inputs on the host and skip the FP64 error checks,
+    so that only this library's kernels run on the GPU (counter collection)."""
     import la_inputs
 
     t0 = time.perf_counter()
-    A, Q, s, V = la_inputs.polar_case_torch(m, n, lo, seeds)
+    A, Q, s, V = la_inputs.polar_case_torch(
+        m, n, lo, seeds, device="cpu" if counter_run else "cuda",
+        progress=lambda w: print(f"[bench] polar input {w} ready after "
+                                 f"{time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                                 flush=True))
     del Q
+    V = V.to("cuda:0")
     torch.cuda.empty_cache()
     sd = torch.from_numpy(s).to("cuda:0")
     Ad = torch.from_numpy(A).to("cuda:0")
@@ -175,7 +183,8 @@ def polar_section(la, torch, m=16384, n=16384, lo=1e-6, seeds=(301, 302, 303)):
         out[name] = {"seconds": round(dt, 3), "iters_precond": info["iters_precond"],
                      "iters_ns": info["iters_ns"], "tflops_algorithmic": round(alg / dt / 1e12, 1),
                      "tflops_paper_equivalent": round(paper_eq / dt / 1e12, 1)}
-        out[name].update(polar_errors(torch, Ad, U, H, V, sd))
+        if not counter_run:
+            out[name].update(polar_errors(torch, Ad, U, H, V, sd))
         print(f"[bench] polar {m}x{n} {name}: {dt:.2f} s, {out[name]}", file=sys.stderr,
               flush=True)
     out["speedup_auto_vs_fp32"] = round(out["fp32"]["seconds"] / out["auto"]["seconds"], 2)
@@ -496,6 +505,10 @@ def main():
     ap.add_argument("--polar-only", action="store_true",
                     help="run only the polar sections (16384^2 and, unless --no-tall, "
                          "131072 x 4096), for profiling their kernels")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="with --polar-only: build the polar inputs on the host and skip "
+                         "the FP64 error checks, so that only this library's kernels run "
+                         "on the GPU (rocprofv3 --pmc runs)")
     ap.add_argument("--only", choices=["BF16X3", "FP32", "BF16X6"], default=None,
                     help="time one precision only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -526,10 +539,11 @@ def main():
         print(json.dumps({"qr": qr_section(la, torch)}), flush=True)
         return
     if args.polar_only:
-        res = {"polar": polar_section(la, torch)}
+        res = {"polar": polar_section(la, torch, counter_run=args.counter_run)}
         torch.cuda.empty_cache()
         if not args.no_tall:
-            res["polar_tall"] = polar_section(la, torch, 131072, 4096, 1e-4, (501, 502, 503))
+            res["polar_tall"] = polar_section(la, torch, 131072, 4096, 1e-4, (501, 502, 503),
+                                              counter_run=args.counter_run)
         print(json.dumps(res), flush=True)
         return
     if args.serving_only:

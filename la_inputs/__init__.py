@@ -134,12 +134,17 @@ def serve_pool(pool_size: int, seed: int, n_lo: int = 128, n_hi: int = 4096):
     return cases
 
 
-def polar_case_torch(m: int, n: int, lo: float, seeds, device="cuda"):
+def polar_case_torch(m: int, n: int, lo: float, seeds, device="cuda", progress=None):
     """Same recipe as polar_case (A = Q diag(s) V^T, Haar Q and V from the QR
     of seeded numpy Gaussians, sign-fixed), with the QR and the product done
     in float64 by torch on `device` so that large sizes are practical.
+    progress, if given, is called with a short message after each factor.
     Returns (A32 host float32, Q dev float64, s host float64, V dev float64)."""
     import torch
+
+    def done(what):
+        if progress is not None:
+            progress(what)
 
     def orth(rows, cols, seed):
         g = torch.from_numpy(rng(seed).standard_normal(size=(rows, cols))).to(device)
@@ -149,8 +154,11 @@ def polar_case_torch(m: int, n: int, lo: float, seeds, device="cuda"):
         return q * d[None, :]
 
     Q = orth(m, n, seeds[0])
+    done(f"Q {m}x{n}")
     V = orth(n, n, seeds[1])
+    done(f"V {n}x{n}")
     s = singular_values(n, lo, seeds[2])
     sd = torch.from_numpy(s).to(device)
     A = ((Q * sd[None, :]) @ V.T.contiguous()).to(torch.float32).cpu().numpy()
+    done(f"A {m}x{n}")
     return A, Q, s, V
