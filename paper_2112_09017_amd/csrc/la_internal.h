@@ -85,6 +85,14 @@ hipError_t launch_pack_x3(const float *X, int64_t ld, int kc, int64_t rows, int6
 // same products in the same order as the 3xBF16 kernel of launch_gemm.
 hipError_t launch_gemm_packed_x3(const GemmDesc &d, hipStream_t s);
 
+// C (rows x cols, ldc) <- C - Y Z with Y (rows x K, k contiguous, ldy) and
+// Z (K x cols, ldz), K <= 128 (qr_update.hip): the short-K update of
+// Algorithm caqr, every element as launch_gemm computes alpha Y Z + beta C
+// with alpha = -1, beta = 1 on the 128 x 128 tile class.
+hipError_t launch_short_update(int prec, const float *Y, int64_t ldy, const float *Z, int64_t ldz,
+                               float *C, int64_t ldc, int64_t rows, int64_t cols, int K,
+                               hipStream_t s);
+
 // Auxiliary kernels (aux_kernels.hip).
 // Sum of squares of an m x n strided matrix into nparts FP64 partials.
 int sumsq_num_partials();

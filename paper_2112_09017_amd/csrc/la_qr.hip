@@ -18,8 +18,9 @@
 //            la_wy, A_l <- [R; 0] and A_r <- A_r - Y (W^T A_r) as two GEMM
 //            launches (the first split along its long K = rows dimension),
 //            with one panel of look-ahead: the next panel's columns are
-//            updated on the caller's stream and the rest on a second stream;
-//            optionally Q = Q_f(0) ... Q_f(last) [I; 0] afterwards.  AUTO runs
+//            updated on the caller's stream and the rest on a second stream
+//            (the update is the short-K kernel of qr_update.hip); optionally
+//            Q = Q_f(0) ... Q_f(last) [I; 0] afterwards.  AUTO runs
 //            the products as 6xBF16: the update's K is only the panel width,
 //            too short for the 3xBF16 products' per-term error (about 2^-16
 //            relative) to average out.
@@ -40,6 +41,13 @@ constexpr int kRows = 256;        // rows of one local factorisation
 constexpr int kMaxPanel = 128;
 constexpr int kMaxLevels = 40;
 constexpr int kMaxSplits = 16;
+// The next panel's product W^T A_next (b x b output, K = the panel's rows) is
+// on the critical path of every panel: it takes up to 64 slices of at least
+// 256 rows, so its launch is short, where the other split products (wide
+// outputs) keep slices of at least 1024 rows.
+constexpr int kMaxSplitsNext = 64;
+constexpr int64_t kMinSliceNext = 256;
+constexpr int64_t kMinSlice = 1024;
 // A Gauss-Jordan pivot of I - Q_1 below this magnitude is reported as the
 // breakdown of eq. (Yamamoto): Y would carry errors of order u / pivot.
 constexpr double kPivotFloor = 1.0 / 65536.0;
@@ -113,8 +121,13 @@ __device__ inline T group_sum(T v)
 // reduce inside the wave (group_sum) without a barrier.
 //
 // Reflection j uses u = x - beta e_j (x = column j from row j down,
-// beta = -sign(x_j) ||x||, norm in FP64) unscaled, H_j = I - kappa u u^T,
-// kappa = 1 / (beta (beta - x_j)).  The owners of column j form u (zero above
+// beta = -sign(x_j) ||x||) unscaled, H_j = I - kappa u u^T,
+// kappa = 1 / (beta (beta - x_j)).  ||x||^2 is summed in FP32, four
+// independent partial sums per lane and then across the lane group, and
+// beta and kappa are formed in FP32: these sit on the one-wave chain between
+// two barriers that every step waits for.  A column whose squares could
+// leave the FP32 range (sum outside [2^-96, 2^96], zero or non-finite) takes
+// FP64 squares, which are exact for FP32 entries, and FP64 beta and kappa.  The owners of column j form u (zero above
 // row j, u_j = x_j - beta on it, x below it) and publish it to one of two LDS
 // buffers with kappa; after one barrier every column c > j forms u^T x_c and
 // x_c -= kappa (u^T x_c) u, and the owners of column j + 1 (already updated)
@@ -150,31 +163,45 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
         f[i] = (col && rlo + i < rows) ? X[(r0 + rlo + i) * ldx + c] : 0.0f;
 
     // owners of column jn (all L lanes): reflection jn from their column.
-    // The column from row jn down (zero above) goes to ubuf[jn & 1] while
-    // ||x||^2 accumulates in FP64 (FP32 products are exact in FP64); the pivot
-    // x_jn is read back from LDS (one wave's LDS accesses complete in order),
-    // and its lane overwrites it with u_jn once beta is known.
+    // The column from row jn down (zero above) goes to ubuf[jn & 1] while its
+    // squares accumulate; the pivot x_jn is read back from LDS (one wave's LDS
+    // accesses complete in order), and its lane overwrites it with u_jn once
+    // beta is known.
     auto prepare = [&](int jn) {
         float *ub = ubuf[jn & 1];
-        double s = 0.0;
+        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < RPL; i += 4) {
             float o[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 o[e] = rlo + i + e < jn ? 0.0f : f[i + e];
-                s = fma((double)o[e], (double)o[e], s);
+                s4[e] = fmaf(o[e], o[e], s4[e]);
             }
             *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
         }
-        const double nrm = sqrt(group_sum<L>(s));
-        const double x0 = ub[jn];
+        const float ss = group_sum<L>((s4[0] + s4[1]) + (s4[2] + s4[3]));
         float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
-        if (nrm > 0.0) {
-            const double bt = x0 >= 0.0 ? -nrm : nrm;
-            u0 = (float)(x0 - bt);
-            kap = (float)(1.0 / (bt * (bt - x0)));
-            beta = (float)bt;
+        if (ss >= 0x1p-96f && ss <= 0x1p96f) {
+            const float nrm = sqrtf(ss), x0 = ub[jn];
+            beta = x0 >= 0.0f ? -nrm : nrm;
+            u0 = x0 - beta;
+            kap = 1.0f / (beta * (beta - x0));
+        } else {
+            double sd = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const double v = rlo + i < jn ? 0.0 : (double)f[i];
+                sd = fma(v, v, sd);
+            }
+            const double nrm = sqrt(group_sum<L>(sd));
+            const double x0 = ub[jn];
+            if (nrm > 0.0) {
+                const double bt = x0 >= 0.0 ? -nrm : nrm;
+                u0 = (float)(x0 - bt);
+                kap = (float)(1.0 / (bt * (bt - x0)));
+                beta = (float)bt;
+            }
         }
         if (rlo == 0) {
             s_u0[jn] = u0;
@@ -581,8 +608,9 @@ size_t wy_bytes(int nc) { return al((size_t)nc * nc * sizeof(float)) + 256; }
 
 // Split count for a GEMM whose output (rows x cols) is small beside its K:
 // enough slices to give every compute unit about two tiles, each slice at
-// least 1024 deep.
-int splits_for(int prec, int64_t rows, int64_t cols, int64_t K, int num_cus)
+// least min_slice deep, at most max_splits.
+int splits_for(int prec, int64_t rows, int64_t cols, int64_t K, int num_cus, int max_splits,
+               int64_t min_slice)
 {
     GemmDesc d;
     memset(&d, 0, sizeof d);
@@ -597,14 +625,14 @@ int splits_for(int prec, int64_t rows, int64_t cols, int64_t K, int num_cus)
     gemm_finalize(d, prec);
     const int64_t tiles = std::max<int64_t>(1, (int64_t)d.tiles_m * d.tiles_n);
     int64_t sp = (2 * num_cus + tiles - 1) / tiles;
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 1024));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, kMaxSplits));
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / min_slice));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, max_splits));
 }
 
 // Split-K GEMMs Z (rows x cols, ld cols) = X^T V with X (K x rows, ldx) and
 // V (K x cols, ldv): the slices are independent problems of one grouped
 // persistent launch (so they run side by side), each writing its own slice
-// of parts (kMaxSplits x rows x cols scratch), summed in slice order.  The
+// of parts (max_splits x rows x cols scratch), summed in slice order.  The
 // descriptors of every such product of a factorisation are built on the host
 // first and uploaded once.
 struct SplitGemm {
@@ -620,9 +648,10 @@ struct SplitBatch {
 };
 
 void add_split(SplitBatch &sb, int prec, const float *X, int64_t ldx, const float *V, int64_t ldv,
-               int64_t rows, int64_t cols, int64_t K, float *Z, float *parts, int num_cus)
+               int64_t rows, int64_t cols, int64_t K, float *Z, float *parts, int num_cus,
+               int max_splits, int64_t min_slice)
 {
-    const int splits = splits_for(prec, rows, cols, K, num_cus);
+    const int splits = splits_for(prec, rows, cols, K, num_cus, max_splits, min_slice);
     const int64_t ks = (K + splits - 1) / splits;
     SplitGemm g;
     g.first_prob = (int)sb.probs.size();
@@ -683,37 +712,13 @@ hipError_t run_split(int prec, const SplitBatch &sb, int which, const GemmDesc *
     return hipGetLastError();
 }
 
-// C (rows x cols, ldc) -= X Z with X (rows x K, ldx) and Z (K x cols, ld cols).
+// C (rows x cols, ldc) -= X Z with X (rows x K, ldx) and Z (K x cols, ld cols):
+// K is the panel width, so the short-K kernel streams C once with its reads
+// issued ahead of the products.
 hipError_t gemm_sub(int prec, const float *X, int64_t ldx, const float *Z, int64_t rows,
                     int64_t cols, int64_t K, float *C, int64_t ldc, hipStream_t s)
 {
-    GemmDesc d;
-    memset(&d, 0, sizeof d);
-    d.A = X;
-    d.lda = ldx;
-    d.a_kcontig = 1;
-    d.B = Z;
-    d.ldb = cols;
-    d.b_kcontig = 0;
-    d.C = C;
-    d.ldc = ldc;
-    d.E = C;
-    d.lde = ldc;
-    d.beta = 1.0f;
-    d.alpha = -1.0f;
-    d.M = rows;
-    d.N = cols;
-    d.K = K;
-    gemm_finalize(d, prec);
-    if (K <= 128 && !d.small) {
-        // K is the panel width: the launch streams C in and out, and the smaller
-        // tile class keeps more tiles in flight (the class never changes a result)
-        d.small = 1;
-        d.tiles_m = (int)((rows + tile_m(prec, 1) - 1) / tile_m(prec, 1));
-        d.tiles_n = (int)((cols + tile_n(prec, 1) - 1) / tile_n(prec, 1));
-        d.num_tiles = d.tiles_m * d.tiles_n;
-    }
-    return launch_gemm(prec, d, s);
+    return launch_short_update(prec, X, ldx, Z, cols, C, ldc, rows, cols, (int)K, s);
 }
 
 // Workspace of la_caqr, in order: Qr (m x b), Rr (b x b), the TSQR tree of an
@@ -744,20 +749,26 @@ CaqrWs caqr_ws(int64_t m, int64_t n, int b, int want_q)
     o += wyb;
     w.z0 = o;
     o += al((size_t)b * b * sizeof(float));
+    // a split product's K is at most m, so it takes at most m / min_slice slices
+    const size_t sp_next = (size_t)std::min<int64_t>(kMaxSplitsNext,
+                                                     std::max<int64_t>(1, m / kMinSliceNext));
+    const size_t sp_wide = (size_t)std::min<int64_t>(kMaxSplits,
+                                                     std::max<int64_t>(1, m / kMinSlice));
     w.parts0 = o;
-    o += al((size_t)kMaxSplits * b * b * sizeof(float));
+    o += al(sp_next * b * b * sizeof(float));
     w.z1 = o;
     o += al((size_t)b * n * sizeof(float));
     w.parts1 = o;
-    o += al((size_t)kMaxSplits * b * n * sizeof(float));
+    o += al(sp_wide * b * n * sizeof(float));
     // split-K descriptors: next-panel and trailing products of every panel,
     // and the Q pass
     const int64_t np = (n + b - 1) / b;
-    const size_t nprod = (size_t)np * (want_q ? 3 : 2);
+    // (a next-panel product has one tile row and one tile column, b <= 128)
+    const size_t nwide = (size_t)np * (want_q ? 2 : 1);
     w.probs = o;
-    o += al(nprod * kMaxSplits * sizeof(GemmDesc));
+    o += al(((size_t)np * sp_next + nwide * sp_wide) * sizeof(GemmDesc));
     w.items = o;
-    o += al(nprod * split_items_bound(n) * sizeof(GroupItem));
+    o += al(((size_t)np * sp_next + nwide * split_items_bound(n)) * sizeof(GroupItem));
     w.bytes = o;
     return w;
 }
@@ -969,12 +980,12 @@ la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, 
         if (nc2 > 0) {
             zn[jp] = (int)sb.gemms.size();
             add_split(sb, pr, wpan(jp), ldwy, A + c * lda + nx, lda, nc, nc2, ml, Z0, P0,
-                      ctx->num_cus);
+                      ctx->num_cus, kMaxSplitsNext, kMinSliceNext);
         }
         if (rest < n) {
             zt[jp] = (int)sb.gemms.size();
             add_split(sb, pr, wpan(jp), ldwy, A + c * lda + rest, lda, nc, n - rest, ml, Z1, P1,
-                      ctx->num_cus);
+                      ctx->num_cus, kMaxSplits, kMinSlice);
         }
     }
     if (Q)
@@ -983,7 +994,7 @@ la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, 
             const int nc = (int)std::min<int64_t>(b, n - c);
             zq[jp] = (int)sb.gemms.size();
             add_split(sb, pr, ypan(jp), n, Q + c * ldq + c, ldq, nc, n - c, ml, Z1, P1,
-                      ctx->num_cus);
+                      ctx->num_cus, kMaxSplits, kMinSlice);
         }
     if (sb.probs.size() * sizeof(GemmDesc) > cw.items - cw.probs ||
         sb.items.size() * sizeof(GroupItem) > cw.bytes - cw.items) {

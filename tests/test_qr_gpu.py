@@ -214,6 +214,23 @@ def test_caqr_r_without_q_and_in_place(la):
     assert np.array_equal(Xh[:320], host(R1)) and np.all(Xh[320:] == 0.0)
 
 
+def test_caqr_huge_leading_dimension(la):
+    """A leading dimension above 2^21 floats takes the short-K update's
+    pointer path (its buffer path keeps a 128-row tile's offsets below 2^31
+    bytes); both paths compute every element identically, so the factors
+    equal those of a contiguous A bit for bit."""
+    m, n = 640, 320
+    A32 = la_inputs.gaussian((m, n), 862)
+    Q1, R1 = la.caqr(dev(A32), panel=64)
+    base = torch.zeros((m, (1 << 21) + 64), dtype=torch.float32, device="cuda")
+    X = base[:, :n]
+    X.copy_(dev(A32))
+    Q2, _ = la.caqr(X, panel=64, inplace=True)
+    assert torch.equal(Q1, Q2)
+    assert torch.equal(torch.triu(X[:n]), R1)
+    assert torch.count_nonzero(base[:, n:]) == 0    # nothing written beyond A
+
+
 def test_caqr_error_paths(la):
     from paper_2112_09017_amd import LAError, Status
     A = dev(la_inputs.gaussian((128, 64), 870))
