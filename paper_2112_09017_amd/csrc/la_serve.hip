@@ -11,7 +11,10 @@
 //      of Algorithm NS_Polar (a preconditioning step, eqs. a_def-RogueMatrix,
 //      or a Newton-Schulz step, eq. NewtonSchulz): one grouped Gram launch and
 //      one grouped update launch per precision and tile class cover all
-//      requests, whatever their sizes;
+//      requests, whatever their sizes; the tick's descriptors and tile items
+//      go up in two copies, and the launches of a phase run side by side on
+//      up to four streams (a launch of a few large-tile problems fills only
+//      part of the device);
 //   3. reduces the new requests' norms and the Newton-Schulz step norms in one
 //      grouped launch and reads them back in one copy: the tick's one wait;
 //   4. applies each request's stop test on the host; finished requests get
@@ -121,6 +124,18 @@ struct Launch {
     std::vector<GroupItem> items;
 };
 
+// A launch whose descriptors and items are in the staging area.
+struct Staged {
+    const Launch *L;
+    const GemmDesc *dd;
+    const GroupItem *di;
+};
+
+// Streams beside the executor's own that a phase's launches run on: the
+// launches of one phase (one per precision and tile class) are independent,
+// and a launch of a few large-tile problems fills only part of the device.
+constexpr int kSide = 3;
+
 void add_problem(std::vector<Launch> &ls, int prec, int akc, int bkc, const GemmDesc &d)
 {
     Launch *L = nullptr;
@@ -183,6 +198,8 @@ struct HipExec {
     char *arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_go = nullptr, ev_side[kSide] = {};
     char *h_stage = nullptr;     // pinned mirror of the reserved area
     double *h_red = nullptr;     // pinned: norms read back
     PinnedPool pool;
@@ -272,6 +289,25 @@ struct HipExec {
         d->cur = 0;
     }
     void retire(serve::Req &) {}
+
+    // streams and events (teardown and failed creation: nothing to report to)
+    void release_streams()
+    {
+        for (int k = 0; k < kSide; ++k) {
+            if (ev_side[k])
+                (void)hipEventDestroy(ev_side[k]);
+            if (side[k])
+                (void)hipStreamDestroy(side[k]);
+            ev_side[k] = nullptr;
+            side[k] = nullptr;
+        }
+        if (ev_go)
+            (void)hipEventDestroy(ev_go);
+        if (stream)
+            (void)hipStreamDestroy(stream);
+        ev_go = nullptr;
+        stream = nullptr;
+    }
     void copy_out(const serve::Req &r, float *U, float *H)
     {
         const DevReq *d = (const DevReq *)r.x;
@@ -281,11 +317,13 @@ struct HipExec {
             memcpy(H, d->hh, (size_t)r.n * r.n * 4);
     }
 
-    // Upload each launch's descriptors and items to the reserved area and run
-    // the grouped kernels; items are ordered by decreasing K so the persistent
-    // workgroups share the work evenly.  Admission keeps a tick's staging
-    // within the area; the check here only guards that bound.
-    hipError_t run_launches(std::vector<Launch> &ls, size_t &dpos, size_t &ipos)
+    // Stage each launch's descriptors and items in the pinned mirror of the
+    // reserved area (descriptors from dpos, items from ipos); items are
+    // ordered by decreasing K so the persistent workgroups share the work
+    // evenly.  Admission keeps a tick's staging within the area; the check
+    // here only guards that bound.
+    hipError_t stage(std::vector<Launch> &ls, size_t &dpos, size_t &ipos,
+                     std::vector<Staged> &out)
     {
         for (auto &L : ls) {
             if (L.items.empty())
@@ -300,22 +338,51 @@ struct HipExec {
                 return hipErrorOutOfMemory;
             memcpy(h_stage + dpos, L.probs.data(), db);
             memcpy(h_stage + kDescBytes + ipos, L.items.data(), ib);
-            GemmDesc *dd = (GemmDesc *)(arena + dpos);
-            GroupItem *di = (GroupItem *)(arena + kDescBytes + ipos);
-            hipError_t e =
-                hipMemcpyAsync(dd, h_stage + dpos, db, hipMemcpyHostToDevice, stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(di, h_stage + kDescBytes + ipos, ib, hipMemcpyHostToDevice,
-                                   stream);
-            if (e == hipSuccess)
-                e = launch_gemm_grouped(L.prec, L.akc, L.bkc, L.small, dd, di,
-                                        (int)L.items.size(), ctx->num_cus, stream);
-            if (e != hipSuccess)
-                return e;
+            out.push_back(Staged{&L, (const GemmDesc *)(arena + dpos),
+                                 (const GroupItem *)(arena + kDescBytes + ipos)});
             dpos += up(db);
             ipos += up(ib);
         }
         return hipSuccess;
+    }
+
+    // One copy for all staged descriptors and one for all staged items.
+    hipError_t upload(size_t dpos, size_t ipos)
+    {
+        hipError_t e = hipSuccess;
+        if (dpos)
+            e = hipMemcpyAsync(arena, h_stage, dpos, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && ipos)
+            e = hipMemcpyAsync(arena + kDescBytes, h_stage + kDescBytes, ipos,
+                               hipMemcpyHostToDevice, stream);
+        return e;
+    }
+
+    // The launches of one phase side by side: the first on the executor's
+    // stream, the others on the side streams after everything already queued
+    // on it; the executor's stream then waits for all of them.
+    hipError_t run_phase(const std::vector<Staged> &st)
+    {
+        if (st.empty())
+            return hipSuccess;
+        const int used = std::min<int>((int)st.size() - 1, kSide);
+        hipError_t e = hipSuccess;
+        if (used > 0)
+            e = hipEventRecord(ev_go, stream);
+        for (int k = 0; k < used && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent(side[k], ev_go, 0);
+        for (size_t i = 0; i < st.size() && e == hipSuccess; ++i) {
+            const Launch &L = *st[i].L;
+            hipStream_t s = i == 0 ? stream : side[(i - 1) % kSide];
+            e = launch_gemm_grouped(L.prec, L.akc, L.bkc, L.small, st[i].dd, st[i].di,
+                                    (int)L.items.size(), ctx->num_cus, s);
+        }
+        for (int k = 0; k < used && e == hipSuccess; ++k) {
+            e = hipEventRecord(ev_side[k], side[k]);
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(stream, ev_side[k], 0);
+        }
+        return e;
     }
 
     la_status tick(const std::vector<serve::Req *> &fresh, const std::vector<serve::Req *> &run,
@@ -365,10 +432,17 @@ struct HipExec {
             add_problem(updates, prec, 1, 0, ud);
         }
         size_t dpos = 0, ipos = 0;
+        std::vector<Staged> sg, su;
         if (e == hipSuccess)
-            e = run_launches(grams, dpos, ipos);
+            e = stage(grams, dpos, ipos, sg);
         if (e == hipSuccess)
-            e = run_launches(updates, dpos, ipos);
+            e = stage(updates, dpos, ipos, su);
+        if (e == hipSuccess)
+            e = upload(dpos, ipos);
+        if (e == hipSuccess)
+            e = run_phase(sg);
+        if (e == hipSuccess)
+            e = run_phase(su);
         // 3. the norms of the new requests and the step norms, one readback
         if (e == hipSuccess && !red.empty()) {
             ReduceItem *dev_ri = (ReduceItem *)(arena + kDescBytes + kItemBytes + kRedItemsOff);
@@ -414,7 +488,12 @@ struct HipExec {
                         gram_desc(d->A, U, d->P, r->m, r->n, 1.0f, 0.0f, 1, r->plan.prec_h));
         }
         size_t dpos = 0, ipos = 0;   // the tick's wait has passed: the area is free
-        hipError_t e = run_launches(hs, dpos, ipos);
+        std::vector<Staged> sh;
+        hipError_t e = stage(hs, dpos, ipos, sh);
+        if (e == hipSuccess)
+            e = upload(dpos, ipos);
+        if (e == hipSuccess)
+            e = run_phase(sh);
         for (serve::Req *r : done) {
             if (e != hipSuccess)
                 break;
@@ -487,6 +566,12 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
     hipError_t e = hipSetDevice(x.device);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+    for (int k = 0; k < kSide && e == hipSuccess; ++k)
+        e = hipStreamCreateWithFlags(&x.side[k], hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&x.ev_go, hipEventDisableTiming);
+    for (int k = 0; k < kSide && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&x.ev_side[k], hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&x.h_stage, kReserve, hipHostMallocDefault);
     if (e == hipSuccess)
@@ -494,8 +579,7 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
                           hipHostMallocDefault);
     if (e != hipSuccess) {
         // cleanup of a failed create: the first error is the one reported
-        if (x.stream)
-            (void)hipStreamDestroy(x.stream);
+        x.release_streams();
         if (x.h_stage)
             (void)hipHostFree(x.h_stage);
         set_error("la_serve_create: %s", hipGetErrorString(e));
@@ -503,7 +587,7 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
     }
     s->core.reset(new (std::nothrow) serve::Core<HipExec>(x, c));
     if (!s->core) {
-        (void)hipStreamDestroy(x.stream);
+        x.release_streams();
         (void)hipHostFree(x.h_stage);
         (void)hipHostFree(x.h_red);
         set_error("la_serve_create: out of host memory");
@@ -552,7 +636,7 @@ la_status la_serve_destroy(la_server *s)
     s->core->shutdown();
     // teardown: an error here has no caller to act on it
     (void)hipStreamSynchronize(s->ex.stream);
-    (void)hipStreamDestroy(s->ex.stream);
+    s->ex.release_streams();
     (void)hipHostFree(s->ex.h_stage);
     (void)hipHostFree(s->ex.h_red);
     s->core.reset();
