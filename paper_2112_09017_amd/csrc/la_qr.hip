@@ -114,6 +114,107 @@ __device__ inline T group_sum(T v)
     return v;
 }
 
+// Q = H_0 ... H_{nc-1} [I; 0] of a block's 64-column reflector set, in
+// compact WY form: H_0 ... H_{nc-1} = I - U T U^T with U = [u_0 ... u_{nc-1}]
+// (u_j zero above row j) and T upper triangular, T^-1 = diag(1/kappa) +
+// N, N the strict upper part of S = U^T U.  So Q = [I; 0] - U Z with
+// Z = T U_top^T (U_top: the first 64 rows of U), and Z = diag(kappa)
+// (U_top^T - N Z), solved from the last row up without a division (a column
+// without a reflection, kappa = 0, gives a zero row of Z and of T).
+//   1. each lane writes its 32 entries of U (zero above the diagonal, u_j on
+//      it, the stored x below) to LDS, row r at r * 64, column j at slot
+//      j ^ (r & 31), so both a row and a column of 32 are conflict-free;
+//   2. three waves form the blocks (0,0), (0,1), (1,1) of S on the matrix
+//      cores (v_mfma_f32_32x32x2f32, K = the block's rows) and write S
+//      transposed (S[i][k] at k * 64 + i);
+//   3. wave 0 solves for Z, lane = column: once row k of Z is final it
+//      subtracts S[i][k] z_k from every row i < k, then writes row k over
+//      column k of S (no longer read);
+//   4. all eight waves form [I; 0] - U Z, 16 blocks of 32 x 32, on the matrix
+//      cores and write it to Q (rows of this block; ldq).
+// f: this lane's 32 rows of column c after the reflections; s_u0 / s_kap:
+// u_j and kappa_j in LDS (read before the space is reused); lds: the
+// kernel's 80 KiB buffer.
+template <int RPL>
+__device__ __forceinline__ void form_q64(const float (&f)[RPL], int c, bool col, int nc, int lane,
+                                         int w, int rlo, int rows, const float *s_u0,
+                                         const float *s_kap, float *lds, float *Qb, int64_t ldq)
+{
+    typedef float f32x16_t __attribute__((ext_vector_type(16)));
+    const float u0c = col ? s_u0[c] : 0.0f;
+    const float kapl = lane < nc ? s_kap[lane] : 0.0f;
+    __syncthreads();   // every wave is past the reflections and has its u_j / kappa
+    float *Us = lds;
+    float *SZ = lds + kRows * 64;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = rlo + i;
+        const float v = (!col || r < c) ? 0.0f : (r == c ? u0c : f[i]);
+        Us[r * 64 + (c ^ (r & 31))] = v;
+    }
+    __syncthreads();
+    const int li = lane & 31, hk = lane >> 5;
+    if (w < 3) {
+        const int bi = w == 2 ? 1 : 0, bj = w == 0 ? 0 : 1;
+        f32x16_t acc = {};
+        for (int k = 0; k < rows; k += 2) {
+            const int r = k + hk;
+            const float a = Us[r * 64 + ((bi * 32 + li) ^ (r & 31))];
+            const float b = Us[r * 64 + ((bj * 32 + li) ^ (r & 31))];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = bi * 32 + 8 * (e >> 2) + 4 * hk + (e & 3), j = bj * 32 + li;
+            SZ[j * 64 + i] = acc[e];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        float z[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i)
+            z[i] = Us[lane * 64 + (i ^ (lane & 31))];   // U_top^T (i, lane) = U (lane, i)
+#pragma unroll
+        for (int k = 63; k >= 0; --k) {
+            z[k] *= __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kapl), k));
+            const float *sk = SZ + k * 64;              // S[0..k-1][k]
+#pragma unroll
+            for (int i = 0; i < (k & ~3); i += 4) {
+                const float4 sv = *reinterpret_cast<const float4 *>(sk + i);
+                z[i] = fmaf(-sv.x, z[k], z[i]);
+                z[i + 1] = fmaf(-sv.y, z[k], z[i + 1]);
+                z[i + 2] = fmaf(-sv.z, z[k], z[i + 2]);
+                z[i + 3] = fmaf(-sv.w, z[k], z[i + 3]);
+            }
+#pragma unroll
+            for (int i = k & ~3; i < k; ++i)
+                z[i] = fmaf(-sk[i], z[k], z[i]);
+            SZ[k * 64 + lane] = z[k];                   // row k of Z
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int bid = 2 * w + q, br = bid >> 1, bc = bid & 1;
+        if (br * 32 >= rows)
+            continue;
+        f32x16_t acc = {};
+        for (int k = 0; k < nc; k += 2) {
+            const int kk = k + hk, r = br * 32 + li;
+            const float a = Us[r * 64 + (kk ^ (r & 31))];
+            const float b = SZ[kk * 64 + bc * 32 + li];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int rr = br * 32 + 8 * (e >> 2) + 4 * hk + (e & 3), cc = bc * 32 + li;
+            if (rr < rows && cc < nc)
+                Qb[(int64_t)rr * ldq + cc] = (rr == cc ? 1.0f : 0.0f) - acc[e];
+        }
+    }
+}
+
 // Householder QR of one row block (rows x nc, rows <= 256, nc <= B) per
 // workgroup of 8 B threads, the block in registers.  Wave w owns columns
 // 8 w .. 8 w + 7; within the wave a column is held by L = 8 consecutive
@@ -127,16 +228,18 @@ __device__ inline T group_sum(T v)
 // beta and kappa are formed in FP32: these sit on the one-wave chain between
 // two barriers that every step waits for.  A column whose squares could
 // leave the FP32 range (sum outside [2^-96, 2^96], zero or non-finite) takes
-// FP64 squares, which are exact for FP32 entries, and FP64 beta and kappa.  The owners of column j form u (zero above
-// row j, u_j = x_j - beta on it, x below it) and publish it to one of two LDS
-// buffers with kappa; after one barrier every column c > j forms u^T x_c and
-// x_c -= kappa (u^T x_c) u, and the owners of column j + 1 (already updated)
-// prepare the next reflection into the other buffer.  One barrier per step.
-// Column j keeps x below the diagonal and the pivot x_j on it; u_j, kappa and
-// beta go to LDS arrays.  R (row block blk of R, ld ldr) is then written from
-// the registers, and Q = H_0 ... H_{nc-1} [I; 0] is formed in place, last
-// reflection first (column j becomes H_j e_j once the columns to its right
-// hold H_{j+1} ... e_c), and written to Q (ldq).  X may equal Q.
+// FP64 squares, which are exact for FP32 entries, and FP64 beta and kappa.
+// The owners of column j form u (zero above row j, u_j = x_j - beta on it,
+// x below it) and publish it to one of two LDS buffers with kappa; after one
+// barrier every column c > j forms u^T x_c and x_c -= kappa (u^T x_c) u, and
+// the owners of column j + 1 (already updated) prepare the next reflection
+// into the other buffer.  One barrier per step.  Column j keeps x below the
+// diagonal and the pivot x_j on it; u_j, kappa and beta go to LDS arrays.
+// R (row block blk of R, ld ldr) is then written from the registers, and
+// Q = H_0 ... H_{nc-1} [I; 0] is formed and written to Q (ldq); X may equal
+// Q.  B = 64: in compact WY form (form_q64), a few parallel steps; B = 128:
+// in place, last reflection first (column j becomes H_j e_j once the
+// columns to its right hold H_{j+1} ... e_c), one barrier per reflection.
 template <int B>
 __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t ldx, Part part,
                                                          int nc, float *Q, int64_t ldq, float *R,
@@ -145,8 +248,13 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     constexpr int CPW = 8;              // columns per wave
     constexpr int L = 64 / CPW;         // lanes per column
     constexpr int RPL = kRows / L;      // rows per lane
-    __shared__ __attribute__((aligned(16))) float ubuf[2][kRows];
-    __shared__ float s_u0[B], s_kap[B], s_beta[B];
+    // LDS: the two u buffers and u_j, kappa, beta during the reflections; for
+    // B = 64 the same space then holds U and S / Z of the compact WY form
+    // (80 KiB in all, so two workgroups share a CU)
+    constexpr int kLdsF = B == 64 ? kRows * 64 + 64 * 64 : 2 * kRows + 3 * B;
+    __shared__ __attribute__((aligned(16))) float lds[kLdsF];
+    float(*ubuf)[kRows] = reinterpret_cast<float(*)[kRows]>(lds);
+    float *s_u0 = lds + 2 * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int c = w * CPW + lane / L;
@@ -268,44 +376,49 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             Rb[(int64_t)rr * ldr + c] = c > rr ? f[i] : (c == rr ? s_beta[rr] : 0.0f);
     }
 
-    if (c == nc - 1)
-        republish(nc - 1);
-    __syncthreads();
-    for (int jv = nc - 1; jv >= 0; --jv) {
-        const int j = __builtin_amdgcn_readfirstlane(jv);
-        const float *ub = ubuf[j & 1];
-        const float kap = s_kap[j], u0 = s_u0[j];
-        float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int i = 0; i < RPL; i += 4) {
-            const float4 uv = *(const float4 *)&ub[rlo + i];
-            const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                u[i + e] = ua[e];
-                d4[e] = fmaf(ua[e], f[i + e], d4[e]);
-            }
-        }
-        const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
-        if (col && c > j) {
-            axpy_u(kap * d);
-        } else if (c == j) {
-            // column j = H_j e_j = e_j - kappa u_j u (u is zero above row j)
-            const float s2 = kap * u0;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i)
-                f[i] = rlo + i == j ? 1.0f : 0.0f;
-            axpy_u(s2);
-        }
-        if (c == j - 1)
-            republish(j - 1);
+    if constexpr (B == 64) {
+        form_q64(f, c, col, nc, lane, w, rlo, rows, s_u0, s_kap, lds, Q + r0 * ldq, ldq);
+        return;
+    } else {
+        if (c == nc - 1)
+            republish(nc - 1);
         __syncthreads();
-    }
+        for (int jv = nc - 1; jv >= 0; --jv) {
+            const int j = __builtin_amdgcn_readfirstlane(jv);
+            const float *ub = ubuf[j & 1];
+            const float kap = s_kap[j], u0 = s_u0[j];
+            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < RPL; i += 4) {
+                const float4 uv = *(const float4 *)&ub[rlo + i];
+                const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    u[i + e] = ua[e];
+                    d4[e] = fmaf(ua[e], f[i + e], d4[e]);
+                }
+            }
+            const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+            if (col && c > j) {
+                axpy_u(kap * d);
+            } else if (c == j) {
+                // column j = H_j e_j = e_j - kappa u_j u (u is zero above row j)
+                const float s2 = kap * u0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    f[i] = rlo + i == j ? 1.0f : 0.0f;
+                axpy_u(s2);
+            }
+            if (c == j - 1)
+                republish(j - 1);
+            __syncthreads();
+        }
 
 #pragma unroll
-    for (int i = 0; i < RPL; ++i)
-        if (col && rlo + i < rows)
-            Q[(r0 + rlo + i) * ldq + c] = f[i];
+        for (int i = 0; i < RPL; ++i)
+            if (col && rlo + i < rows)
+                Q[(r0 + rlo + i) * ldq + c] = f[i];
+    }
 }
 
 // out[r, :] = (in[r, :] - sub [r < nc] e_r^T) M_b for every row r < part.rows,
