@@ -252,9 +252,13 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     // B = 64 the same space then holds U and S / Z of the compact WY form
     // (80 KiB in all, so two workgroups share a CU)
     constexpr int kLdsF = B == 64 ? kRows * 64 + 64 * 64 : 2 * kRows + 3 * B;
+    static_assert(B != 64 || 16 * kRows + 3 * B <= kLdsF, "reflection buffers fit the WY space");
     __shared__ __attribute__((aligned(16))) float lds[kLdsF];
+    // u buffers: B = 64, two sets of 8 (one per sub-panel, alternating);
+    // B = 128, two (alternating reflections)
+    constexpr int kUbufs = B == 64 ? 16 : 2;
     float(*ubuf)[kRows] = reinterpret_cast<float(*)[kRows]>(lds);
-    float *s_u0 = lds + 2 * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
+    float *s_u0 = lds + kUbufs * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int c = w * CPW + lane / L;
@@ -275,8 +279,7 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     // squares accumulate; the pivot x_jn is read back from LDS (one wave's LDS
     // accesses complete in order), and its lane overwrites it with u_jn once
     // beta is known.
-    auto prepare = [&](int jn) {
-        float *ub = ubuf[jn & 1];
+    auto prepare = [&](int jn, float *ub) {
         float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < RPL; i += 4) {
@@ -342,13 +345,8 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             f[i] = fmaf(-sc, u[i], f[i]);
     };
 
-    if (c == 0)
-        prepare(0);
-    __syncthreads();
-    for (int jv = 0; jv < nc; ++jv) {
-        const int j = __builtin_amdgcn_readfirstlane(jv);
-        const float *ub = ubuf[j & 1];
-        const float kap = s_kap[j];
+    // f -= kappa_j (u_j^T f) u_j for this lane's column, u_j read from ub
+    auto reflect = [&](const float *ub, float kap, bool apply) {
         float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < RPL; i += 4) {
@@ -361,11 +359,52 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             }
         }
         const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
-        const float sc = (col && c > j) ? kap * d : 0.0f;
-        axpy_u(sc);
-        if (c == j + 1 && col)
-            prepare(j + 1);
+        axpy_u(apply ? kap * d : 0.0f);
+    };
+
+    if constexpr (B == 64) {
+        // Sub-panel p = wave p's 8 columns.  Wave p applies the reflections of
+        // sub-panel p - 1 to its columns, then forms its own 8 reflections one
+        // after the other, each applied at once to its later columns: all in
+        // one wave, so LDS order within the wave replaces the barrier.  After
+        // one barrier the waves to its right apply those 8 (read from the
+        // sub-panel's buffers) while wave p + 1 starts the same.  8 barriers
+        // instead of 64.
+        const int npan = (nc + 7) / 8;
+        for (int pv = 0; pv < npan; ++pv) {
+            const int p = __builtin_amdgcn_readfirstlane(pv);
+            if (p > 0 && w >= p) {
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = 8 * (p - 1) + jj;
+                    if (j >= nc)
+                        break;
+                    reflect(ubuf[8 * ((p - 1) & 1) + jj], s_kap[j], col);
+                }
+            }
+            if (w == p) {
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = 8 * p + jj;
+                    if (j >= nc)
+                        break;
+                    float *ub = ubuf[8 * (p & 1) + jj];
+                    if (c == j)
+                        prepare(j, ub);
+                    reflect(ub, s_kap[j], col && c > j);
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        if (c == 0)
+            prepare(0, ubuf[0]);
         __syncthreads();
+        for (int jv = 0; jv < nc; ++jv) {
+            const int j = __builtin_amdgcn_readfirstlane(jv);
+            reflect(ubuf[j & 1], s_kap[j], col && c > j);
+            if (c == j + 1 && col)
+                prepare(j + 1, ubuf[(j + 1) & 1]);
+            __syncthreads();
+        }
     }
 
     float *Rb = R + blk * nc * ldr;
