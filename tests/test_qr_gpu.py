@@ -74,7 +74,7 @@ def check_factors(A, Q, R, Qo, Ro, label, tol=TOL):
 
 
 TSQR_SHAPES = [(256, 64), (1000, 64), (300, 37), (600, 100), (131, 100), (64, 64), (1, 1),
-               (5000, 128), (70000, 32), (257, 1)]
+               (5000, 128), (70000, 32), (257, 1), (45, 45), (520, 61)]
 
 
 @pytest.mark.parametrize("shape", TSQR_SHAPES)
@@ -114,6 +114,27 @@ def test_tsqr_special_inputs(la):
     Rh = host(R)
     assert np.all(Rh[:, 5] == 0.0)
     assert np.linalg.norm(A - host(Q) @ Rh) <= TOL * np.linalg.norm(A)
+
+
+def test_tsqr_rank_deficient(la):
+    """Repeated and scaled columns: their parts below the diagonal vanish (up
+    to rounding) once the column they repeat is reflected, so the later
+    reflections come from rounding-level vectors or none at all.  Q stays
+    orthonormal and A = Q R holds to the tolerance; the diagonal of R is
+    negligible in the dependent columns."""
+    A = la_inputs.gaussian((700, 48), 823).astype(np.float64)
+    A[:, 7] = A[:, 3]
+    A[:, 20] = 2.0 * A[:, 5]
+    A[:, 33] = 0.0
+    A32 = A.astype(np.float32)
+    Q, R = la.tsqr(dev(A32))
+    Qh, Rh = host(Q), host(R)
+    A = A32.astype(np.float64)
+    assert np.linalg.norm(A - Qh @ Rh) <= TOL * np.linalg.norm(A)
+    assert np.linalg.norm(Qh.T @ Qh - np.eye(48)) / math.sqrt(48) <= TOL
+    scale = np.max(np.abs(np.diag(Rh)))
+    for j in (7, 20, 33):
+        assert abs(Rh[j, j]) <= 1e-5 * scale
 
 
 @pytest.mark.parametrize("shape", [(300, 64), (5000, 128), (90, 12), (20, 1)])
