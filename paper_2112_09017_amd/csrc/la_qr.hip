@@ -366,7 +366,7 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
         // Sub-panel p = wave p's 8 columns.  Wave p applies the reflections of
         // sub-panel p - 1 to its columns, then forms its own 8 reflections one
         // after the other, each applied at once to its later columns: all in
-        // one wave, so LDS order within the wave replaces the barrier.  After
+        // one wave, so a wave-scope fence and LDS order replace the barrier.  After
         // one barrier the waves to its right apply those 8 (read from the
         // sub-panel's buffers) while wave p + 1 starts the same.  8 barriers
         // instead of 64.
@@ -389,6 +389,10 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
                     float *ub = ubuf[8 * (p & 1) + jj];
                     if (c == j)
                         prepare(j, ub);
+                    // u_j and kappa_j go from the owner lanes to the others
+                    // through LDS: the fence keeps the other lanes' reads
+                    // after the owners' stores (one wave: LDS order holds)
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     reflect(ub, s_kap[j], col && c > j);
                 }
             }
