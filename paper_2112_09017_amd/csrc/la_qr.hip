@@ -291,6 +291,8 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             }
             *(float4 *)&ub[rlo + i] = make_float4(o[0], o[1], o[2], o[3]);
         }
+        // the pivot x_jn, read back below, was stored by one of the owner lanes
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const float ss = group_sum<L>((s4[0] + s4[1]) + (s4[2] + s4[3]));
         float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
         if (ss >= 0x1p-96f && ss <= 0x1p96f) {
