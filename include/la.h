@@ -365,28 +365,34 @@ la_status la_caqr(la_context *ctx, int64_t m, int64_t n, float *A, int64_t lda, 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of polar requests.
  * Requests are admitted while their device footprint fits the arena and a
- * slot is free; every tick advances all active requests by one iteration
- * with grouped launches (one Gram launch and one update launch for all of
- * them), so requests of different sizes and phases share the GPU.
+ * slot is free; every tick advances all active requests of a size band by
+ * one iteration with grouped launches (one Gram launch and one update launch
+ * for all of them), so requests of different sizes and phases share the GPU.
+ * The bands (small and large requests) tick independently on streams of
+ * their own and share the arena and the slots.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int max_slots;     /* requests in flight at once                    [32]   */
     int max_queue;     /* requests waiting for admission                [4096] */
-    int reserved[6];
+    int bands;         /* size bands ticking independently               [2]   */
+                       /*   2: m n^2 <= 2048^3 and larger; 1: one band        */
+    int reserved[5];
 } la_serve_config;
 
 typedef struct {
     uint64_t submitted, completed, failed, ticks;
     int active, queued;
-    double busy_seconds;   /* host wall time spent inside ticks            */
+    double busy_seconds;   /* host wall time with a band inside a tick     */
     size_t arena_high_water;
 } la_serve_stats;
 
 typedef struct la_server la_server;
 
 /* arena: caller-owned device memory (256-byte aligned) the server carves
- * request state from; it is not freed by the library.  cfg may be NULL.
- * Starts one scheduler thread bound to ctx's device. */
+ * request state from (the first 8 MiB hold the bands' launch staging); it is
+ * not freed by the library.  cfg may be NULL.  Starts one scheduler thread
+ * per band, bound to ctx's device.  LA_ERR_INVALID_ARG for bands outside
+ * 0..2. */
 la_status la_serve_create(la_context *ctx, const la_serve_config *cfg,
                           void *arena, size_t arena_bytes, la_server **out);
 

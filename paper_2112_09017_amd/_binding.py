@@ -107,7 +107,7 @@ class InverseInfo(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int), ("max_queue", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("bands", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class ServeStats(ctypes.Structure):

@@ -1,20 +1,25 @@
 // Continuous-batching server of polar requests (la_serve_* in la.h): the HIP
 // executor of the scheduler in serve_core.h.
 //
-// One scheduler thread per server drives a HIP stream in "ticks".  A tick:
-//   1. admits queued requests (FIFO) while a slot is free, the request's
-//      device footprint fits the arena (first-fit allocator) and its launch
-//      descriptors and tile items fit the tick's staging area; for each, the
-//      input is copied in, ||A||_F^2 is summed in FP64 and X0 = A / ||A||_F is
-//      formed on the device from that sum (Algorithm NS_Polar, first step);
-//   2. advances every active request, the new ones included, by one iteration
-//      of Algorithm NS_Polar (a preconditioning step, eqs. a_def-RogueMatrix,
-//      or a Newton-Schulz step, eq. NewtonSchulz): one grouped Gram launch and
-//      one grouped update launch per precision and tile class cover all
-//      requests, whatever their sizes; the tick's descriptors and tile items
-//      go up in two copies, and the launches of a phase run side by side on
-//      up to four streams (a launch of a few large-tile problems fills only
-//      part of the device);
+// Requests are routed by size to one of two bands (square n <= 2048, and
+// larger), each with a scheduler thread, a stream of its own (plus side
+// streams) and a staging area; the bands tick independently and share the
+// arena, the slots and the pinned host buffers.  A band's tick:
+//   1. admits its queued requests (FIFO, and no request overtakes an older
+//      one of the other band for arena or slots) while a slot is free, the
+//      request's device footprint fits the arena (first-fit allocator) and
+//      its launch descriptors and tile items fit the band's staging area; for
+//      each, the input is copied in, ||A||_F^2 is summed in FP64 and
+//      X0 = A / ||A||_F is formed on the device from that sum (Algorithm
+//      NS_Polar, first step);
+//   2. advances every active request of the band, the new ones included, by
+//      one iteration of Algorithm NS_Polar (a preconditioning step, eqs.
+//      a_def-RogueMatrix, or a Newton-Schulz step, eq. NewtonSchulz): one
+//      grouped Gram launch and one grouped update launch per precision and
+//      tile class cover all of them, whatever their sizes; the tick's
+//      descriptors and tile items go up in two copies, and the launches of a
+//      phase run side by side on up to four streams (a launch of a few
+//      large-tile problems fills only part of the device);
 //   3. reduces the new requests' norms and the Newton-Schulz step norms in one
 //      grouped launch and reads them back in one copy: the tick's one wait;
 //   4. applies each request's stop test on the host; finished requests get
@@ -22,6 +27,8 @@
 //      grouped launch, added in FP64 and written to both triangles), their
 //      factors are copied to pinned host buffers and their arena blocks are
 //      released.
+// A small request thus steps at the pace of its own band and not at that of
+// the largest request in flight.
 // Every tile of every request is computed by the same kernel code with the
 // same tile shape as when the request runs alone, so a request's result is
 // bitwise independent of what else is in flight.  Each product accumulates
@@ -44,11 +51,16 @@ namespace la {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kDescBytes = 1u << 20;      // GemmDesc arrays of one staging pass
-constexpr size_t kItemBytes = 6u << 20;      // GroupItem arrays of one staging pass
-constexpr size_t kRedBytes = 1u << 20;       // ReduceItem array + norms read back
-constexpr size_t kReserve = kDescBytes + kItemBytes + kRedBytes;
+// Staging area of one band; kMaxBands of them at the start of the arena.
+constexpr size_t kDescBytes = 512u << 10;    // GemmDesc arrays of one staging pass
+constexpr size_t kItemBytes = 3u << 20;      // GroupItem arrays of one staging pass
+constexpr size_t kRedBytes = 512u << 10;     // ReduceItem array + norms read back
+constexpr size_t kBandReserve = kDescBytes + kItemBytes + kRedBytes;
 constexpr int kMaxSlots = 4096;
+// Size bands: square requests up to n = 2048 (m n^2 <= 2048^3) tick apart
+// from larger ones.
+constexpr int kMaxBands = 2;
+constexpr double kBandWork = 2048.0 * 2048.0 * 2048.0;
 // launch groups of one staging pass: 3 precisions x 2 tile classes x 2 phases,
 // each padded to kAlign
 constexpr int kMaxGroups = 12;
@@ -195,18 +207,19 @@ GemmDesc update_desc(const float *X, const float *P, float *Xn, int64_t m, int64
 struct HipExec {
     la_context *ctx = nullptr;
     int device = 0;
-    char *arena = nullptr;
-    size_t arena_bytes = 0;
+    char *stage_dev = nullptr;   // this band's staging area (kBandReserve bytes)
+    char *req_base = nullptr;    // request state: the arena after every band's staging
+    size_t req_bytes = 0;
     hipStream_t stream = nullptr;
     hipStream_t side[kSide] = {};
     hipEvent_t ev_go = nullptr, ev_side[kSide] = {};
-    char *h_stage = nullptr;     // pinned mirror of the reserved area
+    char *h_stage = nullptr;     // pinned mirror of the staging area
     double *h_red = nullptr;     // pinned: norms read back
-    PinnedPool pool;
+    PinnedPool *pool = nullptr;  // shared by the bands
 
     // ---- the executor interface of serve_core.h
     bool bind() { return hipSetDevice(device) == hipSuccess; }
-    size_t capacity() { return (arena_bytes & ~(kAlign - 1)) - kReserve; }
+    size_t capacity() { return req_bytes; }
     size_t footprint(const serve::Req &r)
     {
         const size_t mn = (size_t)r.m * r.n, nn = (size_t)r.n * r.n;
@@ -244,11 +257,11 @@ struct HipExec {
             return LA_ERR_OUT_OF_MEMORY;
         }
         const size_t mn = (size_t)r.m * r.n, nn = (size_t)r.n * r.n;
-        d->io = (float *)pool.get(mn * 4, &d->io_cls);
-        d->hh = (float *)pool.get(nn * 4, &d->hh_cls);
+        d->io = (float *)pool->get(mn * 4, &d->io_cls);
+        d->hh = (float *)pool->get(nn * 4, &d->hh_cls);
         if (!d->io || !d->hh) {
-            pool.put(d->io, d->io_cls);
-            pool.put(d->hh, d->hh_cls);
+            pool->put(d->io, d->io_cls);
+            pool->put(d->hh, d->hh_cls);
             delete d;
             set_error("la_serve_submit: pinned host allocation failed");
             return LA_ERR_OUT_OF_MEMORY;
@@ -263,15 +276,15 @@ struct HipExec {
         DevReq *d = (DevReq *)r.x;
         if (!d)
             return;
-        pool.put(d->io, d->io_cls);
-        pool.put(d->hh, d->hh_cls);
+        pool->put(d->io, d->io_cls);
+        pool->put(d->hh, d->hh_cls);
         delete d;
         r.x = nullptr;
     }
     void place(serve::Req &r, size_t off)
     {
         DevReq *d = (DevReq *)r.x;
-        char *b = arena + kReserve + off;
+        char *b = req_base + off;
         const size_t mn = (size_t)r.m * r.n, nn = (size_t)r.n * r.n;
         d->A = (float *)b;
         b += up(mn * 4);
@@ -338,8 +351,8 @@ struct HipExec {
                 return hipErrorOutOfMemory;
             memcpy(h_stage + dpos, L.probs.data(), db);
             memcpy(h_stage + kDescBytes + ipos, L.items.data(), ib);
-            out.push_back(Staged{&L, (const GemmDesc *)(arena + dpos),
-                                 (const GroupItem *)(arena + kDescBytes + ipos)});
+            out.push_back(Staged{&L, (const GemmDesc *)(stage_dev + dpos),
+                                 (const GroupItem *)(stage_dev + kDescBytes + ipos)});
             dpos += up(db);
             ipos += up(ib);
         }
@@ -351,9 +364,9 @@ struct HipExec {
     {
         hipError_t e = hipSuccess;
         if (dpos)
-            e = hipMemcpyAsync(arena, h_stage, dpos, hipMemcpyHostToDevice, stream);
+            e = hipMemcpyAsync(stage_dev, h_stage, dpos, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess && ipos)
-            e = hipMemcpyAsync(arena + kDescBytes, h_stage + kDescBytes, ipos,
+            e = hipMemcpyAsync(stage_dev + kDescBytes, h_stage + kDescBytes, ipos,
                                hipMemcpyHostToDevice, stream);
         return e;
     }
@@ -406,7 +419,7 @@ struct HipExec {
         // 2. one step for every running request
         std::vector<Launch> grams, updates;
         std::vector<ReduceItem> red;
-        double *dev_d = (double *)(arena + kDescBytes + kItemBytes);
+        double *dev_d = (double *)(stage_dev + kDescBytes + kItemBytes);
         for (serve::Req *r : fresh)
             red.push_back(ReduceItem{((DevReq *)r->x)->scal, 1, dev_d + red.size()});
         for (serve::Req *r : run) {
@@ -445,7 +458,8 @@ struct HipExec {
             e = run_phase(su);
         // 3. the norms of the new requests and the step norms, one readback
         if (e == hipSuccess && !red.empty()) {
-            ReduceItem *dev_ri = (ReduceItem *)(arena + kDescBytes + kItemBytes + kRedItemsOff);
+            ReduceItem *dev_ri =
+                (ReduceItem *)(stage_dev + kDescBytes + kItemBytes + kRedItemsOff);
             char *hst = h_stage + kDescBytes + kItemBytes + kRedItemsOff;
             memcpy(hst, red.data(), red.size() * sizeof(ReduceItem));
             e = hipMemcpyAsync(dev_ri, hst, red.size() * sizeof(ReduceItem),
@@ -524,8 +538,25 @@ struct HipExec {
 using namespace la;
 
 struct la_server {
-    HipExec ex;
+    PinnedPool pool;
+    HipExec ex[kMaxBands];
+    int bands = 0;
     std::unique_ptr<serve::Core<HipExec>> core;
+
+    // streams, events and pinned staging of every band (teardown and failed
+    // creation: nothing to report to)
+    void release()
+    {
+        for (HipExec &x : ex) {
+            x.release_streams();
+            if (x.h_stage)
+                (void)hipHostFree(x.h_stage);
+            if (x.h_red)
+                (void)hipHostFree(x.h_red);
+            x.h_stage = nullptr;
+            x.h_red = nullptr;
+        }
+    }
 };
 
 extern "C" {
@@ -543,10 +574,15 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
         set_error("la_serve_create: arena must be 256-byte aligned");
         return LA_ERR_INVALID_ARG;
     }
+    constexpr size_t kReserve = kMaxBands * kBandReserve;
     if (arena_bytes < kReserve + (64u << 20)) {
         set_error("la_serve_create: arena of %zu bytes is below the %zu-byte minimum",
                   arena_bytes, kReserve + (64u << 20));
         return LA_ERR_OUT_OF_MEMORY;
+    }
+    if (cfg && (cfg->bands < 0 || cfg->bands > kMaxBands)) {
+        set_error("la_serve_create: bands = %d (0 for the default, 1 or 2)", cfg->bands);
+        return LA_ERR_INVALID_ARG;
     }
     std::unique_ptr<la_server> s(new (std::nothrow) la_server);
     if (!s) {
@@ -558,38 +594,42 @@ la_status la_serve_create(la_context *ctx, const la_serve_config *cfg, void *are
         c.max_slots = std::min(cfg->max_slots, kMaxSlots);
     if (cfg && cfg->max_queue > 0)
         c.max_queue = cfg->max_queue;
-    HipExec &x = s->ex;
-    x.ctx = ctx;
-    x.device = ctx->device;
-    x.arena = (char *)arena;
-    x.arena_bytes = arena_bytes;
-    hipError_t e = hipSetDevice(x.device);
-    if (e == hipSuccess)
+    s->bands = cfg && cfg->bands > 0 ? cfg->bands : kMaxBands;
+    if (s->bands > 1)
+        c.band_work.push_back(kBandWork);
+    hipError_t e = hipSetDevice(ctx->device);
+    std::vector<HipExec *> bands;
+    for (int b = 0; b < s->bands && e == hipSuccess; ++b) {
+        HipExec &x = s->ex[b];
+        x.ctx = ctx;
+        x.device = ctx->device;
+        x.stage_dev = (char *)arena + b * kBandReserve;
+        x.req_base = (char *)arena + kReserve;
+        x.req_bytes = (arena_bytes & ~(kAlign - 1)) - kReserve;
+        x.pool = &s->pool;
         e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
-    for (int k = 0; k < kSide && e == hipSuccess; ++k)
-        e = hipStreamCreateWithFlags(&x.side[k], hipStreamNonBlocking);
-    if (e == hipSuccess)
-        e = hipEventCreateWithFlags(&x.ev_go, hipEventDisableTiming);
-    for (int k = 0; k < kSide && e == hipSuccess; ++k)
-        e = hipEventCreateWithFlags(&x.ev_side[k], hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&x.h_stage, kReserve, hipHostMallocDefault);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&x.h_red, 2 * kMaxSlots * sizeof(double),
-                          hipHostMallocDefault);
+        for (int k = 0; k < kSide && e == hipSuccess; ++k)
+            e = hipStreamCreateWithFlags(&x.side[k], hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&x.ev_go, hipEventDisableTiming);
+        for (int k = 0; k < kSide && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&x.ev_side[k], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&x.h_stage, kBandReserve, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&x.h_red, 2 * kMaxSlots * sizeof(double),
+                              hipHostMallocDefault);
+        bands.push_back(&x);
+    }
     if (e != hipSuccess) {
         // cleanup of a failed create: the first error is the one reported
-        x.release_streams();
-        if (x.h_stage)
-            (void)hipHostFree(x.h_stage);
+        s->release();
         set_error("la_serve_create: %s", hipGetErrorString(e));
         return LA_ERR_DEVICE;
     }
-    s->core.reset(new (std::nothrow) serve::Core<HipExec>(x, c));
+    s->core.reset(new (std::nothrow) serve::Core<HipExec>(bands, c));
     if (!s->core) {
-        x.release_streams();
-        (void)hipHostFree(x.h_stage);
-        (void)hipHostFree(x.h_red);
+        s->release();
         set_error("la_serve_create: out of host memory");
         return LA_ERR_OUT_OF_MEMORY;
     }
@@ -625,7 +665,7 @@ la_status la_serve_stats_get(la_server *s, la_serve_stats *out)
         return LA_ERR_INVALID_ARG;
     }
     *out = s->core->stats();
-    out->arena_high_water += kReserve;
+    out->arena_high_water += kMaxBands * kBandReserve;
     return LA_OK;
 }
 
@@ -635,11 +675,10 @@ la_status la_serve_destroy(la_server *s)
         return LA_OK;
     s->core->shutdown();
     // teardown: an error here has no caller to act on it
-    (void)hipStreamSynchronize(s->ex.stream);
-    s->ex.release_streams();
-    (void)hipHostFree(s->ex.h_stage);
-    (void)hipHostFree(s->ex.h_red);
+    for (int b = 0; b < s->bands; ++b)
+        (void)hipStreamSynchronize(s->ex[b].stream);
     s->core.reset();
+    s->release();
     delete s;
     return LA_OK;
 }

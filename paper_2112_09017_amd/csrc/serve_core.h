@@ -1,15 +1,18 @@
 // serve_core.h -- host side of the continuous-batching polar server: request
-// registry, FIFO queue, admission by arena footprint, slots and per-tick
+// registry, FIFO queues, admission by arena footprint, slots and per-tick
 // staging capacity, the per-tick advance of every active request by one step
 // of Algorithm NS_Polar (section III.D) with its stop test, completion,
-// failure handling and statistics.  Plain C++17 with no HIP: the device work
+// failure handling and statistics.  Requests are routed by size (m n^2) to
+// bands; each band has an executor and a scheduler thread of its own and
+// ticks independently of the others, while the arena, the slots and the
+// order of admission are shared.  Plain C++17 with no HIP: the device work
 // of a tick is delegated to an executor, so the same scheduler runs with the
 // HIP executor of la_serve.hip and with a scripted executor on the CPU
 // (tests), where it can be built with thread and address sanitizers.
 //
 // Executor interface (duck-typed; every call is made by the scheduler thread
-// unless stated):
-//   bool bind();                              // once, on the scheduler thread
+// of the executor's band unless stated):
+//   bool bind();                              // once, on that thread
 //   size_t capacity();                        // arena bytes requests may use
 //   size_t footprint(const Req &);            // arena bytes of one request
 //   void stage_need(const Req &, size_t *descs, size_t *items);
@@ -125,6 +128,7 @@ struct Req {
     la_status status = LA_OK;
     size_t off = 0, bytes = 0;         // arena block
     size_t descs = 0, items = 0;       // staging per tick
+    int band = 0;                      // size band (scheduler thread and executor)
     StopState stop{};
     bool finished = false;             // no more steps
     la_polar_info info{};
@@ -141,20 +145,33 @@ struct Req {
 struct Config {
     int max_slots = 32;
     int max_queue = 4096;
+    // Size bands: a request with m n^2 <= band_work[i] (the first such i)
+    // ticks in band i, a larger one in the last band.  Each band has an
+    // executor and a scheduler thread of its own, so a small request's ticks
+    // do not wait for a large request's steps.  One entry fewer than bands.
+    std::vector<double> band_work;
 };
 
 template <class Exec>
 class Core {
   public:
-    Core(Exec &ex, const Config &cfg) : ex_(ex), cfg_(cfg)
+    // One executor per band (at least one); every executor reports the same
+    // capacity(), the bytes of the arena area that all bands share.
+    Core(const std::vector<Exec *> &bands, const Config &cfg) : cfg_(cfg)
     {
-        alloc_.init(0, ex_.capacity());
+        for (Exec *e : bands) {
+            bands_.emplace_back(new Band);
+            bands_.back()->ex = e;
+        }
+        alloc_.init(0, bands_[0]->ex->capacity());
     }
+    Core(Exec &ex, const Config &cfg) : Core(std::vector<Exec *>{&ex}, cfg) {}
     ~Core() { shutdown(); }
 
     void start()
     {
-        worker_ = std::thread([this] { run(); });
+        for (size_t b = 0; b < bands_.size(); ++b)
+            bands_[b]->worker = std::thread([this, b] { run(*bands_[b]); });
     }
 
     // Stops the scheduler; requests not yet polled are dropped.
@@ -167,14 +184,18 @@ class Core {
             stop_ = true;
             cv_.notify_all();
         }
-        if (worker_.joinable())
-            worker_.join();
+        for (auto &b : bands_)
+            if (b->worker.joinable())
+                b->worker.join();
         std::lock_guard<std::mutex> g(mu_);
         for (auto &kv : all_)
-            ex_.drop(*kv.second);
+            bands_[kv.second->band]->ex->drop(*kv.second);
         all_.clear();
-        queue_.clear();
-        active_.clear();
+        for (auto &b : bands_) {
+            b->queue.clear();
+            b->active.clear();
+        }
+        queued_ = active_ = 0;
         stopped_ = true;
     }
 
@@ -201,45 +222,49 @@ class Core {
         r->m = m;
         r->n = n;
         r->plan = plan;
+        r->band = band_of(m, n);
         r->info.last_delta = INFINITY;
         r->info.stop_reason = 2;
-        r->bytes = ex_.footprint(*r);
-        ex_.stage_need(*r, &r->descs, &r->items);
+        Band &B = *bands_[r->band];
+        r->bytes = B.ex->footprint(*r);
+        B.ex->stage_need(*r, &r->descs, &r->items);
         {
             std::lock_guard<std::mutex> g(mu_);
             if (fatal_ != LA_OK) {
                 set_error("la_serve_submit: server stopped after a device error");
                 return fatal_;
             }
-            if (r->bytes > alloc_.capacity() || r->descs > ex_.desc_capacity() ||
-                r->items > ex_.item_capacity()) {
+            if (r->bytes > alloc_.capacity() || r->descs > B.ex->desc_capacity() ||
+                r->items > B.ex->item_capacity()) {
                 set_error("la_serve_submit: request needs %zu arena bytes, %zu descriptors and "
                           "%zu tile items; the server holds %zu, %zu and %zu",
-                          r->bytes, r->descs, r->items, alloc_.capacity(), ex_.desc_capacity(),
-                          ex_.item_capacity());
+                          r->bytes, r->descs, r->items, alloc_.capacity(), B.ex->desc_capacity(),
+                          B.ex->item_capacity());
                 return LA_ERR_TOO_LARGE;
             }
-            if ((int)queue_.size() >= cfg_.max_queue) {
+            if (queued_ >= cfg_.max_queue) {
                 set_error("la_serve_submit: queue full (%d)", cfg_.max_queue);
                 return LA_ERR_QUEUE_FULL;
             }
         }
-        st = ex_.stage_input(*r, A, lda);
+        st = B.ex->stage_input(*r, A, lda);
         if (st != LA_OK)
             return st;
         r->t_submit = now_s();
         std::lock_guard<std::mutex> g(mu_);
         if (fatal_ != LA_OK || stop_) {
-            ex_.drop(*r);
+            B.ex->drop(*r);
             set_error("la_serve_submit: server stopped");
             return fatal_ != LA_OK ? fatal_ : LA_ERR_DEVICE;
         }
         r->id = next_id_++;
         *id = r->id;
-        queue_.push_back(r.get());
+        B.queue.push_back(r.get());
         all_.emplace(r->id, std::move(r));
+        ++queued_;
+        ++gen_;
         stats_.submitted++;
-        stats_.queued = (int)queue_.size();
+        stats_.queued = queued_;
         cv_.notify_all();
         return LA_OK;
     }
@@ -259,13 +284,14 @@ class Core {
             r = std::move(it->second);
             all_.erase(it);
         }
+        Exec &ex = *bands_[r->band]->ex;
         if (r->status == LA_OK || r->status == LA_ERR_NOT_CONVERGED)
-            ex_.copy_out(*r, U, H);
+            ex.copy_out(*r, U, H);
         if (info)
             *info = r->info;
         if (req_status)
             *req_status = r->status;
-        ex_.drop(*r);
+        ex.drop(*r);
         return LA_OK;
     }
 
@@ -279,24 +305,42 @@ class Core {
     int active_count()
     {
         std::lock_guard<std::mutex> g(mu_);
-        return (int)active_.size();
+        return active_;
     }
 
   private:
-    Exec &ex_;
+    struct Band {
+        Exec *ex = nullptr;
+        std::deque<Req *> queue;
+        std::vector<Req *> active;     // changed by this band's thread only
+        size_t descs_used = 0, items_used = 0;   // staging of the active requests
+        std::thread worker;
+    };
+
     Config cfg_;
+    std::vector<std::unique_ptr<Band>> bands_;
     Arena alloc_;
     std::mutex mu_;
     std::condition_variable cv_;
-    std::deque<Req *> queue_;
-    std::vector<Req *> active_;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all_;
     uint64_t next_id_ = 1;
+    int queued_ = 0, active_ = 0;      // over all bands
+    int in_tick_ = 0;                  // bands inside a tick
+    uint64_t gen_ = 0;                 // bumped when a request arrives or leaves
+    double busy_t0_ = 0;
     bool stop_ = false, stopped_ = false;
     la_status fatal_ = LA_OK;
     la_serve_stats stats_{};
-    size_t descs_used_ = 0, items_used_ = 0;   // staging of the active requests
-    std::thread worker_;
+
+    int band_of(int64_t m, int64_t n) const
+    {
+        const double w = (double)m * (double)n * (double)n;
+        const int last = (int)bands_.size() - 1;
+        for (int b = 0; b < last && b < (int)cfg_.band_work.size(); ++b)
+            if (w <= cfg_.band_work[b])
+                return b;
+        return last;
+    }
 
     // under mu_: request r leaves the server with status st
     void complete_locked(Req *r, la_status st, double t)
@@ -314,81 +358,138 @@ class Core {
     }
 
     // under mu_: every queued request fails with the server's fatal status
-    void fail_queue_locked()
+    void fail_queues_locked()
     {
         const double t = now_s();
-        for (Req *r : queue_)
-            complete_locked(r, fatal_, t);
-        queue_.clear();
+        for (auto &b : bands_) {
+            for (Req *r : b->queue)
+                complete_locked(r, fatal_, t);
+            b->queue.clear();
+        }
+        queued_ = 0;
         stats_.queued = 0;
         cv_.notify_all();
     }
 
-    void run()
+    // under mu_, on B's thread: B's active requests fail with the fatal status
+    // (a device error in another band)
+    void fail_active_locked(Band &B)
     {
-        if (!ex_.bind()) {
+        const double t = now_s();
+        for (Req *r : B.active) {
+            B.ex->retire(*r);
+            complete_locked(r, fatal_, t);
+            alloc_.release(r->off, r->bytes);
+        }
+        active_ -= (int)B.active.size();
+        if (!B.active.empty())
+            ++gen_;
+        B.active.clear();
+        B.descs_used = B.items_used = 0;
+        stats_.active = active_;
+        cv_.notify_all();
+    }
+
+    bool any_queued_locked() const { return queued_ > 0; }
+
+    void run(Band &B)
+    {
+        if (!B.ex->bind()) {
             std::unique_lock<std::mutex> g(mu_);
             fatal_ = LA_ERR_DEVICE;
             for (;;) {
-                fail_queue_locked();
-                cv_.wait(g, [&] { return stop_ || !queue_.empty(); });
+                fail_queues_locked();
+                cv_.wait(g, [&] { return stop_ || any_queued_locked(); });
                 if (stop_)
                     return;
             }
         }
+        // A band with requests in flight ticks back to back; one whose queue
+        // is held up (arena or slots taken by the other band, or an older
+        // request there) waits until a request arrives or leaves.
+        uint64_t seen = ~(uint64_t)0;
         for (;;) {
             {
                 std::unique_lock<std::mutex> g(mu_);
-                cv_.wait(g, [&] { return stop_ || !queue_.empty() || !active_.empty(); });
+                cv_.wait(g, [&] {
+                    return stop_ || !B.active.empty() || (!B.queue.empty() && gen_ != seen) ||
+                           (fatal_ != LA_OK && any_queued_locked());
+                });
                 if (stop_)
                     return;
                 if (fatal_ != LA_OK) {
-                    fail_queue_locked();
+                    fail_active_locked(B);
+                    fail_queues_locked();
                     continue;
                 }
+                seen = gen_;
             }
-            tick();
+            tick(B);
         }
     }
 
-    void tick()
+    // under mu_: admission of B's queued requests, FIFO within the band, while
+    // a slot, the arena and the band's staging hold the request.  Across
+    // bands the order of submission is kept for the arena and the slots: a
+    // request is admitted only if the older requests at the heads of the
+    // other bands' queues would still find room.
+    void admit_locked(Band &B, std::vector<Req *> &fresh)
     {
-        const double t0 = now_s();
+        while (!B.queue.empty() && active_ < cfg_.max_slots) {
+            Req *r = B.queue.front();
+            if (B.descs_used + r->descs > B.ex->desc_capacity() ||
+                B.items_used + r->items > B.ex->item_capacity())
+                break;
+            size_t held = 0;
+            int held_slots = 0;
+            for (auto &o : bands_)
+                if (o.get() != &B && !o->queue.empty() && o->queue.front()->id < r->id) {
+                    held += o->queue.front()->bytes;
+                    ++held_slots;
+                }
+            if (active_ + 1 + held_slots > cfg_.max_slots)
+                break;
+            if (held && alloc_.capacity() - alloc_.used() < r->bytes + held)
+                break;
+            size_t off;
+            if (!alloc_.alloc(r->bytes, &off))
+                break;
+            B.queue.pop_front();
+            --queued_;
+            r->off = off;
+            r->state = ACTIVE;
+            B.descs_used += r->descs;
+            B.items_used += r->items;
+            B.ex->place(*r, off);
+            B.active.push_back(r);
+            ++active_;
+            fresh.push_back(r);
+        }
+        stats_.queued = queued_;
+        stats_.active = active_;
+        stats_.arena_high_water = alloc_.high_water();
+    }
+
+    void tick(Band &B)
+    {
+        Exec &ex = *B.ex;
         std::vector<Req *> fresh, run;
         {
-            // admission: FIFO while a slot, the arena and the tick's staging
-            // hold the request
             std::lock_guard<std::mutex> g(mu_);
-            while (!queue_.empty() && (int)active_.size() < cfg_.max_slots) {
-                Req *r = queue_.front();
-                if (descs_used_ + r->descs > ex_.desc_capacity() ||
-                    items_used_ + r->items > ex_.item_capacity())
-                    break;
-                size_t off;
-                if (!alloc_.alloc(r->bytes, &off))
-                    break;
-                queue_.pop_front();
-                r->off = off;
-                r->state = ACTIVE;
-                descs_used_ += r->descs;
-                items_used_ += r->items;
-                ex_.place(*r, off);
-                active_.push_back(r);
-                fresh.push_back(r);
-            }
-            stats_.queued = (int)queue_.size();
-            stats_.active = (int)active_.size();
-            stats_.arena_high_water = alloc_.high_water();
-            for (Req *r : active_)
+            if (in_tick_++ == 0)
+                busy_t0_ = now_s();
+            admit_locked(B, fresh);
+            for (Req *r : B.active)
                 if (!r->finished)
                     run.push_back(r);
         }
+        const bool work = !run.empty() || !fresh.empty();
         std::vector<double> fro2(fresh.size(), 0.0), delta2;
-        la_status st = run.empty() && fresh.empty() ? LA_OK : ex_.tick(fresh, run, fro2, delta2);
+        la_status st = work ? ex.tick(fresh, run, fro2, delta2) : LA_OK;
         if (st != LA_OK) {
             std::lock_guard<std::mutex> g(mu_);
             fatal_ = LA_ERR_DEVICE;
-            for (Req *r : active_) {
+            for (Req *r : B.active) {
                 r->status = LA_ERR_DEVICE;
                 r->finished = true;
             }
@@ -431,7 +532,7 @@ class Core {
             }
         }
         std::vector<Req *> done;
-        for (Req *r : active_)     // only this thread changes active_
+        for (Req *r : B.active)     // only this thread changes B.active
             if (r->finished)
                 done.push_back(r);
         if (!done.empty()) {
@@ -439,7 +540,7 @@ class Core {
             for (Req *r : done)
                 if (r->status == LA_OK || r->status == LA_ERR_NOT_CONVERGED)
                     ok.push_back(r);
-            la_status fs = (st == LA_OK && !ok.empty()) ? ex_.finish(ok) : LA_OK;
+            la_status fs = (st == LA_OK && !ok.empty()) ? ex.finish(ok) : LA_OK;
             const double t1 = now_s();
             std::lock_guard<std::mutex> g(mu_);
             if (fs != LA_OK)
@@ -448,21 +549,25 @@ class Core {
                 la_status rs = r->status;
                 if (fs != LA_OK && (rs == LA_OK || rs == LA_ERR_NOT_CONVERGED))
                     rs = LA_ERR_DEVICE;
-                ex_.retire(*r);
+                ex.retire(*r);
                 complete_locked(r, rs, t1);
                 alloc_.release(r->off, r->bytes);
-                descs_used_ -= r->descs;
-                items_used_ -= r->items;
-                active_.erase(std::find(active_.begin(), active_.end(), r));
+                B.descs_used -= r->descs;
+                B.items_used -= r->items;
+                B.active.erase(std::find(B.active.begin(), B.active.end(), r));
+                --active_;
             }
+            ++gen_;
             cv_.notify_all();
         }
         std::lock_guard<std::mutex> g(mu_);
-        stats_.ticks++;
-        stats_.busy_seconds += now_s() - t0;
-        stats_.active = (int)active_.size();
+        if (work)
+            stats_.ticks++;
+        if (--in_tick_ == 0)
+            stats_.busy_seconds += now_s() - busy_t0_;
+        stats_.active = active_;
         if (fatal_ != LA_OK)
-            fail_queue_locked();
+            fail_queues_locked();
     }
 };
 

@@ -15,10 +15,11 @@ class Server:
 
     ``arena_bytes`` of device memory (a torch allocation owned by this object)
     holds every admitted request's state; requests wait in the queue until
-    their footprint fits and a slot is free."""
+    their footprint fits and a slot is free.  ``bands`` (0: the library's
+    default of 2) is the number of size bands that tick independently."""
 
     def __init__(self, arena_bytes: int, device: int = 0, max_slots: int = 32,
-                 max_queue: int = 4096):
+                 max_queue: int = 4096, bands: int = 0):
         self._arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=f"cuda:{device}")
         base = self._arena.data_ptr()
         self._base = (base + 255) & ~255
@@ -26,6 +27,7 @@ class Server:
         cfg = ServeConfig()
         cfg.max_slots = max_slots
         cfg.max_queue = max_queue
+        cfg.bands = bands
         out = ctypes.c_void_p()
         check(lib().la_serve_create(context(device), ctypes.byref(cfg), self._base, arena_bytes,
                                     ctypes.byref(out)))

@@ -55,7 +55,17 @@ struct FakeState {
     int64_t m = 0, n = 0;
 };
 
+// Observations shared by the executors of a core's size bands.
+struct Obs {
+    std::mutex mu;
+    std::map<size_t, size_t> blocks;   // offset -> bytes of active requests
+    bool overlap = false;
+    std::vector<uint64_t> admitted;
+    int live = 0, max_live = 0;
+};
+
 struct Fake {
+    Obs *obs = nullptr;         // shared with the other bands' executors
     size_t cap = 1 << 20;
     size_t dcap = 64, icap = 4096;
     bool bind_ok = true;
@@ -112,6 +122,15 @@ struct Fake {
         admitted.push_back(r.id);
         live.insert(&r);
         max_active = std::max(max_active, (int)live.size());
+        if (obs) {
+            std::lock_guard<std::mutex> o(obs->mu);
+            for (auto &b : obs->blocks)
+                if (off < b.first + b.second && b.first < off + r.bytes)
+                    obs->overlap = true;
+            obs->blocks[off] = r.bytes;
+            obs->admitted.push_back(r.id);
+            obs->max_live = std::max(obs->max_live, ++obs->live);
+        }
     }
     la_status tick(const std::vector<Req *> &fresh, const std::vector<Req *> &run,
                    std::vector<double> &fro2, std::vector<double> &delta2)
@@ -179,6 +198,11 @@ struct Fake {
         std::lock_guard<std::mutex> g(mu);
         blocks.erase(r.off);
         live.erase(&r);
+        if (obs) {
+            std::lock_guard<std::mutex> o(obs->mu);
+            obs->blocks.erase(r.off);
+            --obs->live;
+        }
     }
     void copy_out(const Req &r, float *U, float *H)
     {
@@ -606,6 +630,178 @@ static void test_threads_and_shutdown()
     printf("threads_and_shutdown: ok\n");
 }
 
+// Two size bands: 12 x 12 and 16 x 16 requests (m n^2 <= 16^3) in band 0,
+// larger ones in band 1.
+static Config band_cfg(int slots)
+{
+    Config cfg;
+    cfg.max_slots = slots;
+    cfg.band_work.push_back(16.0 * 16.0 * 16.0);
+    return cfg;
+}
+
+static void test_bands_route_and_mix()
+{
+    Obs obs;
+    Fake f0, f1;
+    f0.obs = f1.obs = &obs;
+    Config cfg = band_cfg(8);
+    Core<Fake> c({&f0, &f1}, cfg);
+    c.start();
+    std::vector<Sub> subs;
+    std::vector<uint64_t> small, large;
+    const int64_t sizes[][2] = {{8, 8}, {24, 16}, {16, 16}, {40, 12}, {12, 12}, {64, 32}};
+    for (int i = 0; i < 18; ++i) {
+        const int64_t m = sizes[i % 6][0], n = sizes[i % 6][1];
+        subs.push_back(submit_one(c, m, n, std::pow(10.0, 1 + i % 5), i));
+        (m * n * n <= 16 * 16 * 16 ? small : large).push_back(subs.back().id);
+    }
+    for (Sub &s : subs) {
+        la_status rs;
+        la_polar_info info;
+        std::vector<float> U;
+        CHECK(wait_done(c, s, &rs, &info, &U));
+        check_result(s, rs, info, U);
+    }
+    CHECK(f0.admitted == small);   // each band admits its own, in order
+    CHECK(f1.admitted == large);
+    CHECK(!obs.overlap && !f0.stage_over && !f1.stage_over);
+    CHECK(obs.max_live <= cfg.max_slots && obs.live == 0);
+    const la_serve_stats st = c.stats();
+    CHECK(st.completed == subs.size() && st.failed == 0);
+    CHECK(st.ticks == (uint64_t)(f0.ticks + f1.ticks));
+    printf("bands_route_and_mix: %d + %d ticks, max active %d\n", f0.ticks, f1.ticks,
+           obs.max_live);
+}
+
+// A band held inside a tick does not hold up the other band.
+static void test_bands_tick_independently()
+{
+    Obs obs;
+    Fake f0, f1;
+    f0.obs = f1.obs = &obs;
+    std::mutex gm;
+    std::condition_variable gcv;
+    bool open = false;
+    f1.gate = [&] {
+        std::unique_lock<std::mutex> g(gm);
+        gcv.wait(g, [&] { return open; });
+    };
+    Core<Fake> c({&f0, &f1}, band_cfg(8));
+    c.start();
+    Sub big = submit_one(c, 32, 32, 1e4, 1);
+    while (c.active_count() < 1)
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    std::vector<Sub> subs;
+    for (int i = 0; i < 6; ++i)
+        subs.push_back(submit_one(c, 12, 12, 1e3, 10 + i));
+    for (Sub &s : subs) {
+        la_status rs;
+        la_polar_info info;
+        std::vector<float> U;
+        CHECK(wait_done(c, s, &rs, &info, &U));
+        check_result(s, rs, info, U);
+    }
+    la_status rs;
+    CHECK(c.poll(big.id, nullptr, nullptr, nullptr, &rs) == LA_ERR_NOT_READY);
+    {
+        std::lock_guard<std::mutex> g(gm);
+        open = true;
+    }
+    gcv.notify_all();
+    la_polar_info info;
+    std::vector<float> U;
+    CHECK(wait_done(c, big, &rs, &info, &U));
+    check_result(big, rs, info, U);
+    printf("bands_tick_independently: ok\n");
+}
+
+// No request overtakes an older one of the other band for the arena or for
+// a slot: S1 (band 0) holds what B (band 1) needs; S2 (band 0, younger than
+// B) waits for B.
+static void test_bands_keep_submission_order()
+{
+    for (int by_slots = 0; by_slots < 2; ++by_slots) {
+        Obs obs;
+        Fake f0, f1;
+        f0.obs = f1.obs = &obs;
+        // a 32 x 32 request takes 16384 bytes, an 8 x 8 one 1024
+        if (!by_slots)
+            f0.cap = f1.cap = 16384 + 512;
+        std::mutex gm;
+        std::condition_variable gcv;
+        bool open = false;
+        f0.gate = [&] {
+            std::unique_lock<std::mutex> g(gm);
+            gcv.wait(g, [&] { return open; });
+        };
+        Core<Fake> c({&f0, &f1}, band_cfg(by_slots ? 1 : 8));
+        c.start();
+        Sub s1 = submit_one(c, 8, 8, 1e3, 1);
+        while (c.active_count() < 1)
+            std::this_thread::sleep_for(std::chrono::microseconds(100));
+        Sub b = submit_one(c, 32, 32, 1e3, 2);
+        Sub s2 = submit_one(c, 8, 8, 1e3, 3);
+        {
+            std::lock_guard<std::mutex> g(gm);
+            open = true;
+        }
+        gcv.notify_all();
+        for (Sub *s : {&s1, &b, &s2}) {
+            la_status rs;
+            la_polar_info info;
+            std::vector<float> U;
+            CHECK(wait_done(c, *s, &rs, &info, &U));
+            check_result(*s, rs, info, U);
+        }
+        const std::vector<uint64_t> order = {s1.id, b.id, s2.id};
+        CHECK(obs.admitted == order);
+        CHECK(obs.max_live == 1 && !obs.overlap);
+        printf("bands_keep_submission_order (%s): ok\n", by_slots ? "slots" : "arena");
+    }
+}
+
+// A device error in one band fails the other band's requests too.
+static void test_bands_device_error()
+{
+    Obs obs;
+    Fake f0, f1;
+    f0.obs = f1.obs = &obs;
+    f1.fail_tick = 0;
+    std::mutex gm;
+    std::condition_variable gcv;
+    bool open = false;
+    f0.gate = [&] {
+        std::unique_lock<std::mutex> g(gm);
+        gcv.wait(g, [&] { return open; });
+    };
+    Core<Fake> c({&f0, &f1}, band_cfg(8));
+    c.start();
+    Sub s = submit_one(c, 12, 12, 1e5, 1);
+    while (c.active_count() < 1)
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
+    Sub b = submit_one(c, 32, 32, 1e3, 2);
+    la_status rs;
+    la_polar_info info;
+    std::vector<float> U;
+    CHECK(wait_done(c, b, &rs, &info, &U));
+    CHECK(rs == LA_ERR_DEVICE);
+    {
+        std::lock_guard<std::mutex> g(gm);
+        open = true;
+    }
+    gcv.notify_all();
+    CHECK(wait_done(c, s, &rs, &info, &U));
+    CHECK(rs == LA_ERR_DEVICE);
+    uint64_t id;
+    std::vector<float> A(64, 1.0f);
+    CHECK(c.submit(8, 8, A.data(), 8, nullptr, &id) == LA_ERR_DEVICE);
+    CHECK(c.active_count() == 0 && obs.live == 0);
+    const la_serve_stats st = c.stats();
+    CHECK(st.failed == 2 && st.completed == 0);
+    printf("bands_device_error: ok\n");
+}
+
 int main(int argc, char **argv)
 {
     test_mix_and_counts();
@@ -614,6 +810,10 @@ int main(int argc, char **argv)
     test_nonfinite_cap_and_errors();
     test_device_errors();
     test_threads_and_shutdown();
+    test_bands_route_and_mix();
+    test_bands_tick_independently();
+    test_bands_keep_submission_order();
+    test_bands_device_error();
     if (g_fail) {
         fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;

@@ -3,7 +3,8 @@
 * a request's factors are bitwise identical alone and in a mix of sizes and
   phases (every tile is computed the same way whatever shares the launch);
 * requests overlap on the device (shared ticks) and are admitted by HBM
-  footprint (a tight arena forces waiting, never overflow);
+  footprint (a tight arena forces waiting, never overflow); the two size
+  bands give the same bits as one band for all sizes;
 * every result meets the polar tolerances and matches the FP64 oracle's H;
 * error paths: non-finite input fails alone, too-large and queue-full are
   rejected at submit, unknown and twice-polled ids are reported.
@@ -120,6 +121,16 @@ def test_large_tile_requests_mix_equals_alone(la):
         mix = wait_all(srv, ids, timeout=300)
         st = srv.stats()
     assert st["completed"] == len(ids)
+    # the big requests tick in the large band, the small ones in the small
+    # band; one band for all of them gives the same bits
+    inputs = [small[0].A32, big[0][0], small[1].A32, big[1][0], small[2].A32, small[3].A32]
+    with la.Server(8 << 30, max_slots=16, bands=1) as one:
+        ids1 = [one.submit(A) for A in inputs]
+        mix1 = wait_all(one, ids1, timeout=300)
+    for i, i1 in zip(ids, ids1):
+        assert mix[i][0] == mix1[i1][0] == la.Status.OK
+        assert np.array_equal(mix[i][1], mix1[i1][1]) and np.array_equal(mix[i][2], mix1[i1][2])
+        assert mix[i][3] == mix1[i1][3]
     for (A, s, V), i in zip(big, (ids[1], ids[3])):
         status, U, H, info = mix[i]
         assert status == la.Status.OK
@@ -157,6 +168,10 @@ def test_tight_arena_admission(la):
 
 def test_error_paths(la):
     good = la_inputs.polar_case(128, 128, 1e-2, seeds=(970, 971, 972))
+    for bands in (-1, 3):
+        with pytest.raises(la.LAError) as e:
+            la.Server(256 << 20, bands=bands)
+        assert e.value.status == la.Status.INVALID_ARG
     with la.Server(256 << 20, max_slots=4, max_queue=3) as srv:
         with pytest.raises(la.LAError) as e:
             srv.submit(np.ones((8192, 8192), np.float32))
