@@ -252,13 +252,16 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     // B = 64 the same space then holds U and S / Z of the compact WY form
     // (80 KiB in all, so two workgroups share a CU)
     constexpr int kLdsF = B == 64 ? kRows * 64 + 64 * 64 : 2 * kRows + 3 * B;
-    static_assert(B != 64 || 16 * kRows + 3 * B <= kLdsF, "reflection buffers fit the WY space");
+    static_assert(B != 64 || 64 * kRows + 3 * B + 1 <= kLdsF,
+                  "reflection buffers fit the WY space");
     __shared__ __attribute__((aligned(16))) float lds[kLdsF];
-    // u buffers: B = 64, two sets of 8 (one per sub-panel, alternating);
-    // B = 128, two (alternating reflections)
-    constexpr int kUbufs = B == 64 ? 16 : 2;
+    // u buffers: B = 64, one per reflection (each stays until every wave has
+    // applied it); B = 128, two (alternating reflections)
+    constexpr int kUbufs = B == 64 ? 64 : 2;
     float(*ubuf)[kRows] = reinterpret_cast<float(*)[kRows]>(lds);
     float *s_u0 = lds + kUbufs * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
+    // B = 64: reflections published so far (u_j, kappa_j, beta_j in LDS)
+    int *s_pub = reinterpret_cast<int *>(s_beta + B);
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int c = w * CPW + lane / L;
@@ -365,41 +368,56 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
     };
 
     if constexpr (B == 64) {
-        // Sub-panel p = wave p's 8 columns.  Wave p applies the reflections of
-        // sub-panel p - 1 to its columns, then forms its own 8 reflections one
-        // after the other, each applied at once to its later columns: all in
-        // one wave, so a wave-scope fence and LDS order replace the barrier.  After
-        // one barrier the waves to its right apply those 8 (read from the
-        // sub-panel's buffers) while wave p + 1 starts the same.  8 barriers
-        // instead of 64.
-        const int npan = (nc + 7) / 8;
-        for (int pv = 0; pv < npan; ++pv) {
-            const int p = __builtin_amdgcn_readfirstlane(pv);
-            if (p > 0 && w >= p) {
-                for (int jj = 0; jj < 8; ++jj) {
-                    const int j = 8 * (p - 1) + jj;
-                    if (j >= nc)
+        // Wave w owns columns 8 w .. 8 w + 7 and applies the reflections in
+        // order: those of the waves to its left as they are published, then
+        // its own, each formed by the owner lanes of its column (prepare),
+        // published, and applied at once to the wave's later columns.  A
+        // reflection is published by a workgroup-scope release store of the
+        // count of published reflections after its u_j, kappa_j and beta_j
+        // are in LDS; a wave waits for reflection j with acquire loads of
+        // that count.  No barrier: a wave starts its own columns as soon as
+        // it has applied the last reflection of the wave to its left.  Every
+        // wait is for a reflection that a wave to the left publishes without
+        // waiting on this one; it is bounded all the same, and a wait that
+        // runs out marks the block's R with NaN instead of hanging.
+        if (t == 0)
+            *s_pub = 0;
+        __syncthreads();
+        bool timed_out = false;
+        const int own = __builtin_amdgcn_readfirstlane(w * CPW);
+        for (int jv = 0; jv < nc; ++jv) {
+            const int j = __builtin_amdgcn_readfirstlane(jv);
+            float *ub = ubuf[j];
+            if (j < own) {
+                if (w * CPW >= nc)
+                    break;            // no column of this wave
+                int spins = 0;
+                while (__hip_atomic_load(s_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <=
+                       j) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1 << 22)) {
+                        timed_out = true;
                         break;
-                    reflect(ubuf[8 * ((p - 1) & 1) + jj], s_kap[j], col);
+                    }
                 }
+                reflect(ub, s_kap[j], col);
+            } else if (j < own + CPW) {
+                if (c == j)
+                    prepare(j, ub);
+                // u_j and kappa_j go from the owner lanes to the rest of the
+                // wave through LDS: the fence keeps the other lanes' reads
+                // after the owners' stores (one wave: LDS order holds); the
+                // release publishes them to the other waves
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __hip_atomic_store(s_pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                reflect(ub, s_kap[j], col && c > j);
+            } else {
+                break;
             }
-            if (w == p) {
-                for (int jj = 0; jj < 8; ++jj) {
-                    const int j = 8 * p + jj;
-                    if (j >= nc)
-                        break;
-                    float *ub = ubuf[8 * (p & 1) + jj];
-                    if (c == j)
-                        prepare(j, ub);
-                    // u_j and kappa_j go from the owner lanes to the others
-                    // through LDS: the fence keeps the other lanes' reads
-                    // after the owners' stores (one wave: LDS order holds)
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    reflect(ub, s_kap[j], col && c > j);
-                }
-            }
-            __syncthreads();
         }
+        __syncthreads();
+        if (timed_out)
+            f[0] = NAN;
     } else {
         if (c == 0)
             prepare(0, ubuf[0]);
