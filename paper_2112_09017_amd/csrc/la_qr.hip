@@ -230,11 +230,13 @@ __device__ __forceinline__ void form_q64(const float (&f)[RPL], int c, bool col,
 // leave the FP32 range (sum outside [2^-96, 2^96], zero or non-finite) takes
 // FP64 squares, which are exact for FP32 entries, and FP64 beta and kappa.
 // The owners of column j form u (zero above row j, u_j = x_j - beta on it,
-// x below it) and publish it to one of two LDS buffers with kappa; after one
-// barrier every column c > j forms u^T x_c and x_c -= kappa (u^T x_c) u, and
-// the owners of column j + 1 (already updated) prepare the next reflection
-// into the other buffer.  One barrier per step.  Column j keeps x below the
-// diagonal and the pivot x_j on it; u_j, kappa and beta go to LDS arrays.
+// x below it) and publish it to an LDS buffer with kappa; every column c > j
+// then forms u^T x_c and x_c -= kappa (u^T x_c) u.  B = 128: two buffers
+// (alternating steps) and one barrier per step, the owners of column j + 1
+// (already updated) preparing the next reflection meanwhile.  B = 64: one
+// buffer per reflection and no barrier (a count of published reflections
+// orders the waves; see the loop).  Column j keeps x below the diagonal and
+// the pivot x_j on it; u_j, kappa and beta go to LDS arrays.
 // R (row block blk of R, ld ldr) is then written from the registers, and
 // Q = H_0 ... H_{nc-1} [I; 0] is formed and written to Q (ldq); X may equal
 // Q.  B = 64: in compact WY form (form_q64), a few parallel steps; B = 128:
