@@ -114,6 +114,84 @@ __device__ inline T group_sum(T v)
     return v;
 }
 
+// Sum over the 64 lanes of a wave, returned as a wave-uniform value: DPP
+// within rows of 16 lanes (lane ^ 1, lane ^ 2, half-row and row mirrors),
+// then row 0 into row 1 and row 2 into row 3 (row_bcast:15), rows 0 + 1 into
+// rows 2 and 3 (row_bcast:31); lane 63 ends with the total.
+template <int CTRL, int ROWS>
+__device__ inline float bcast_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ inline double bcast_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float wave_sum(float v)
+{
+    v += dpp_f32<0xB1>(v);
+    v += dpp_f32<0x4E>(v);
+    v += dpp_f32<0x141>(v);          // row_half_mirror
+    v += dpp_f32<0x140>(v);          // row_mirror: each row of 16 holds its sum
+    v += bcast_f32<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += bcast_f32<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+// wave_sum of v[first .. N - 1], the N - first sums step by step side by side
+// (each step a DPP add: the moves read zero outside their rows)
+template <int CTRL, int ROWS = 0xF>
+__device__ inline float dppz_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int N>
+__device__ inline void wave_sums(float (&v)[N], int first)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0xB1>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0x4E>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0x141>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0x140>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0x142, 0xA>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] += dppz_f32<0x143, 0xC>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (k >= first)
+            v[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[k]), 63));
+}
+__device__ inline double wave_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    v += bcast_f64<0x142, 0xA>(v);
+    v += bcast_f64<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
 // Q = H_0 ... H_{nc-1} [I; 0] of a block's 64-column reflector set, in
 // compact WY form: H_0 ... H_{nc-1} = I - U T U^T with U = [u_0 ... u_{nc-1}]
 // (u_j zero above row j) and T upper triangular, T^-1 = diag(1/kappa) +
@@ -132,26 +210,19 @@ __device__ inline T group_sum(T v)
 //      column k of S (no longer read);
 //   4. all eight waves form [I; 0] - U Z, 16 blocks of 32 x 32, on the matrix
 //      cores and write it to Q (rows of this block; ldq).
-// f: this lane's 32 rows of column c after the reflections; s_u0 / s_kap:
-// u_j and kappa_j in LDS (read before the space is reused); lds: the
-// kernel's 80 KiB buffer.
-template <int RPL>
-__device__ __forceinline__ void form_q64(const float (&f)[RPL], int c, bool col, int nc, int lane,
-                                         int w, int rlo, int rows, const float *s_u0,
+// write_u(Us): stores this thread's entries of U (step 1), given the values it
+// read from LDS before the call (the space is reused); s_kap: kappa_j in LDS
+// (read before the reuse); lds: the kernel's 80 KiB buffer.
+template <class WriteU>
+__device__ __forceinline__ void form_q64(WriteU write_u, int nc, int lane, int w, int rows,
                                          const float *s_kap, float *lds, float *Qb, int64_t ldq)
 {
     typedef float f32x16_t __attribute__((ext_vector_type(16)));
-    const float u0c = col ? s_u0[c] : 0.0f;
     const float kapl = lane < nc ? s_kap[lane] : 0.0f;
     __syncthreads();   // every wave is past the reflections and has its u_j / kappa
     float *Us = lds;
     float *SZ = lds + kRows * 64;
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        const int r = rlo + i;
-        const float v = (!col || r < c) ? 0.0f : (r == c ? u0c : f[i]);
-        Us[r * 64 + (c ^ (r & 31))] = v;
-    }
+    write_u(Us);
     __syncthreads();
     const int li = lane & 31, hk = lane >> 5;
     if (w < 3) {
@@ -215,11 +286,12 @@ __device__ __forceinline__ void form_q64(const float (&f)[RPL], int c, bool col,
     }
 }
 
-// Householder QR of one row block (rows x nc, rows <= 256, nc <= B) per
-// workgroup of 8 B threads, the block in registers.  Wave w owns columns
+// Householder QR of one row block (rows x nc, rows <= 256, 64 < nc <= 128)
+// per workgroup of 1024 threads, the block in registers.  Wave w owns columns
 // 8 w .. 8 w + 7; within the wave a column is held by L = 8 consecutive
 // lanes, each with RPL = 32 consecutive rows, so the column dot products
-// reduce inside the wave (group_sum) without a barrier.
+// reduce inside the wave (group_sum) without a barrier.  (Blocks of at most
+// 64 columns: qr_block64_kernel.)
 //
 // Reflection j uses u = x - beta e_j (x = column j from row j down,
 // beta = -sign(x_j) ||x||) unscaled, H_j = I - kappa u u^T,
@@ -230,40 +302,29 @@ __device__ __forceinline__ void form_q64(const float (&f)[RPL], int c, bool col,
 // leave the FP32 range (sum outside [2^-96, 2^96], zero or non-finite) takes
 // FP64 squares, which are exact for FP32 entries, and FP64 beta and kappa.
 // The owners of column j form u (zero above row j, u_j = x_j - beta on it,
-// x below it) and publish it to an LDS buffer with kappa; every column c > j
-// then forms u^T x_c and x_c -= kappa (u^T x_c) u.  B = 128: two buffers
-// (alternating steps) and one barrier per step, the owners of column j + 1
-// (already updated) preparing the next reflection meanwhile.  B = 64: one
-// buffer per reflection and no barrier (a count of published reflections
-// orders the waves; see the loop).  Column j keeps x below the diagonal and
-// the pivot x_j on it; u_j, kappa and beta go to LDS arrays.
+// x below it) and publish it to one of two LDS buffers with kappa; after one
+// barrier every column c > j forms u^T x_c and x_c -= kappa (u^T x_c) u, and
+// the owners of column j + 1 (already updated) prepare the next reflection
+// into the other buffer.  One barrier per step.  Column j keeps x below the
+// diagonal and the pivot x_j on it; u_j, kappa and beta go to LDS arrays.
 // R (row block blk of R, ld ldr) is then written from the registers, and
-// Q = H_0 ... H_{nc-1} [I; 0] is formed and written to Q (ldq); X may equal
-// Q.  B = 64: in compact WY form (form_q64), a few parallel steps; B = 128:
-// in place, last reflection first (column j becomes H_j e_j once the
+// Q = H_0 ... H_{nc-1} [I; 0] is formed in place and written to Q (ldq; X
+// may equal Q): last reflection first (column j becomes H_j e_j once the
 // columns to its right hold H_{j+1} ... e_c), one barrier per reflection.
 template <int B>
 __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t ldx, Part part,
                                                          int nc, float *Q, int64_t ldq, float *R,
                                                          int64_t ldr)
 {
+    static_assert(B == 128, "blocks of at most 64 columns: qr_block64_kernel");
     constexpr int CPW = 8;              // columns per wave
     constexpr int L = 64 / CPW;         // lanes per column
     constexpr int RPL = kRows / L;      // rows per lane
-    // LDS: the two u buffers and u_j, kappa, beta during the reflections; for
-    // B = 64 the same space then holds U and S / Z of the compact WY form
-    // (80 KiB in all, so two workgroups share a CU)
-    constexpr int kLdsF = B == 64 ? kRows * 64 + 64 * 64 : 2 * kRows + 3 * B;
-    static_assert(B != 64 || 64 * kRows + 3 * B + 1 <= kLdsF,
-                  "reflection buffers fit the WY space");
+    // LDS: the two u buffers (alternating reflections) and u_j, kappa, beta
+    constexpr int kLdsF = 2 * kRows + 3 * B;
     __shared__ __attribute__((aligned(16))) float lds[kLdsF];
-    // u buffers: B = 64, one per reflection (each stays until every wave has
-    // applied it); B = 128, two (alternating reflections)
-    constexpr int kUbufs = B == 64 ? 64 : 2;
     float(*ubuf)[kRows] = reinterpret_cast<float(*)[kRows]>(lds);
-    float *s_u0 = lds + kUbufs * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
-    // B = 64: reflections published so far (u_j, kappa_j, beta_j in LDS)
-    int *s_pub = reinterpret_cast<int *>(s_beta + B);
+    float *s_u0 = lds + 2 * kRows, *s_kap = s_u0 + B, *s_beta = s_kap + B;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int c = w * CPW + lane / L;
@@ -369,68 +430,15 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
         axpy_u(apply ? kap * d : 0.0f);
     };
 
-    if constexpr (B == 64) {
-        // Wave w owns columns 8 w .. 8 w + 7 and applies the reflections in
-        // order: those of the waves to its left as they are published, then
-        // its own, each formed by the owner lanes of its column (prepare),
-        // published, and applied at once to the wave's later columns.  A
-        // reflection is published by a workgroup-scope release store of the
-        // count of published reflections after its u_j, kappa_j and beta_j
-        // are in LDS; a wave waits for reflection j with acquire loads of
-        // that count.  No barrier: a wave starts its own columns as soon as
-        // it has applied the last reflection of the wave to its left.  Every
-        // wait is for a reflection that a wave to the left publishes without
-        // waiting on this one; it is bounded all the same, and a wait that
-        // runs out marks the block's R with NaN instead of hanging.
-        if (t == 0)
-            *s_pub = 0;
+    if (c == 0)
+        prepare(0, ubuf[0]);
+    __syncthreads();
+    for (int jv = 0; jv < nc; ++jv) {
+        const int j = __builtin_amdgcn_readfirstlane(jv);
+        reflect(ubuf[j & 1], s_kap[j], col && c > j);
+        if (c == j + 1 && col)
+            prepare(j + 1, ubuf[(j + 1) & 1]);
         __syncthreads();
-        bool timed_out = false;
-        const int own = __builtin_amdgcn_readfirstlane(w * CPW);
-        for (int jv = 0; jv < nc; ++jv) {
-            const int j = __builtin_amdgcn_readfirstlane(jv);
-            float *ub = ubuf[j];
-            if (j < own) {
-                if (w * CPW >= nc)
-                    break;            // no column of this wave
-                int spins = 0;
-                while (__hip_atomic_load(s_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <=
-                       j) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1 << 22)) {
-                        timed_out = true;
-                        break;
-                    }
-                }
-                reflect(ub, s_kap[j], col);
-            } else if (j < own + CPW) {
-                if (c == j)
-                    prepare(j, ub);
-                // u_j and kappa_j go from the owner lanes to the rest of the
-                // wave through LDS: the fence keeps the other lanes' reads
-                // after the owners' stores (one wave: LDS order holds); the
-                // release publishes them to the other waves
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __hip_atomic_store(s_pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                reflect(ub, s_kap[j], col && c > j);
-            } else {
-                break;
-            }
-        }
-        __syncthreads();
-        if (timed_out)
-            f[0] = NAN;
-    } else {
-        if (c == 0)
-            prepare(0, ubuf[0]);
-        __syncthreads();
-        for (int jv = 0; jv < nc; ++jv) {
-            const int j = __builtin_amdgcn_readfirstlane(jv);
-            reflect(ubuf[j & 1], s_kap[j], col && c > j);
-            if (c == j + 1 && col)
-                prepare(j + 1, ubuf[(j + 1) & 1]);
-            __syncthreads();
-        }
     }
 
     float *Rb = R + blk * nc * ldr;
@@ -441,49 +449,246 @@ __global__ __launch_bounds__(8 * B) void qr_block_kernel(const float *X, int64_t
             Rb[(int64_t)rr * ldr + c] = c > rr ? f[i] : (c == rr ? s_beta[rr] : 0.0f);
     }
 
-    if constexpr (B == 64) {
-        form_q64(f, c, col, nc, lane, w, rlo, rows, s_u0, s_kap, lds, Q + r0 * ldq, ldq);
-        return;
-    } else {
-        if (c == nc - 1)
-            republish(nc - 1);
-        __syncthreads();
-        for (int jv = nc - 1; jv >= 0; --jv) {
-            const int j = __builtin_amdgcn_readfirstlane(jv);
-            const float *ub = ubuf[j & 1];
-            const float kap = s_kap[j], u0 = s_u0[j];
-            float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (c == nc - 1)
+        republish(nc - 1);
+    __syncthreads();
+    for (int jv = nc - 1; jv >= 0; --jv) {
+        const int j = __builtin_amdgcn_readfirstlane(jv);
+        const float *ub = ubuf[j & 1];
+        const float kap = s_kap[j], u0 = s_u0[j];
+        float d4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int i = 0; i < RPL; i += 4) {
-                const float4 uv = *(const float4 *)&ub[rlo + i];
-                const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
+        for (int i = 0; i < RPL; i += 4) {
+            const float4 uv = *(const float4 *)&ub[rlo + i];
+            const float ua[4] = {uv.x, uv.y, uv.z, uv.w};
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    u[i + e] = ua[e];
-                    d4[e] = fmaf(ua[e], f[i + e], d4[e]);
-                }
+            for (int e = 0; e < 4; ++e) {
+                u[i + e] = ua[e];
+                d4[e] = fmaf(ua[e], f[i + e], d4[e]);
             }
-            const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
-            if (col && c > j) {
-                axpy_u(kap * d);
-            } else if (c == j) {
-                // column j = H_j e_j = e_j - kappa u_j u (u is zero above row j)
-                const float s2 = kap * u0;
-#pragma unroll
-                for (int i = 0; i < RPL; ++i)
-                    f[i] = rlo + i == j ? 1.0f : 0.0f;
-                axpy_u(s2);
-            }
-            if (c == j - 1)
-                republish(j - 1);
-            __syncthreads();
         }
+        const float d = group_sum<L>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+        if (col && c > j) {
+            axpy_u(kap * d);
+        } else if (c == j) {
+            // column j = H_j e_j = e_j - kappa u_j u (u is zero above row j)
+            const float s2 = kap * u0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                f[i] = rlo + i == j ? 1.0f : 0.0f;
+            axpy_u(s2);
+        }
+        if (c == j - 1)
+            republish(j - 1);
+        __syncthreads();
+    }
 
 #pragma unroll
-        for (int i = 0; i < RPL; ++i)
-            if (col && rlo + i < rows)
-                Q[(r0 + rlo + i) * ldq + c] = f[i];
+    for (int i = 0; i < RPL; ++i)
+        if (col && rlo + i < rows)
+            Q[(r0 + rlo + i) * ldq + c] = f[i];
+}
+
+// Householder QR of one row block (rows x nc, rows <= 256, nc <= 64) per
+// workgroup of 8 waves, the block in registers with the rows across the
+// lanes: lane l holds rows 4 l .. 4 l + 3 of its wave's 8 columns (wave w:
+// columns 8 w .. 8 w + 7).  A column vector such as u_j is then spread over
+// the lanes of every wave alike, so the wave that forms a reflection keeps
+// u_j in registers and a column dot product is a sum over the wave
+// (wave_sum: DPP and one readlane).
+//
+// Reflection j uses u = x - beta e_j (x = column j from row j down,
+// beta = -sign(x_j) ||x||) unscaled, H_j = I - kappa u u^T,
+// kappa = 1 / (beta (beta - x_j)); ||x||^2, beta and kappa in FP32, or in
+// FP64 (squares exact for FP32 entries) when the FP32 sum of squares leaves
+// [2^-96, 2^96] (zero or non-finite included).  Each wave applies the
+// reflections in order: those of the waves to its left as they are
+// published (u_j from LDS, then u_j^T x_c and x_c -= kappa (u^T x_c) u for its
+// 8 columns), then its own, each formed from its column, published and
+// applied at once to the wave's later columns.  A reflection is published
+// by a workgroup-scope release store of the count of published reflections
+// after u_j, kappa_j and beta_j are in LDS; a wave waits for reflection j
+// with acquire loads of that count.  No barrier until all reflections are
+// done: a wave starts its own columns once it has applied the last
+// reflection of the wave to its left.  Every wait is for a reflection that a
+// wave to its left publishes without waiting on this one; it is bounded all
+// the same, and a wait that runs out marks the block's R with NaN instead of
+// hanging.  Column j keeps x below the diagonal and the pivot x_j on it.
+// R (row block blk of R, ld ldr) is then written from the registers, and
+// Q = H_0 ... H_{nc-1} [I; 0] is formed in compact WY form (form_q64) and
+// written to Q (ldq); X may equal Q.
+__global__ __launch_bounds__(512) void qr_block64_kernel(const float *X, int64_t ldx, Part part,
+                                                         int nc, float *Q, int64_t ldq, float *R,
+                                                         int64_t ldr)
+{
+    constexpr int CPW = 8;              // columns per wave
+    constexpr int RPL = kRows / 64;     // rows per lane
+    // LDS: u_j of every reflection (each stays until every wave has applied
+    // it), u_j's pivot entry, kappa, beta and the count of published
+    // reflections; the same space then holds U and S / Z of the compact WY
+    // form (80 KiB in all, so two workgroups share a CU)
+    constexpr int kLdsF = kRows * 64 + 64 * 64;
+    static_assert(64 * kRows + 3 * 64 + 1 <= kLdsF, "reflection buffers fit the WY space");
+    __shared__ __attribute__((aligned(16))) float lds[kLdsF];
+    float(*ubuf)[kRows] = reinterpret_cast<float(*)[kRows]>(lds);
+    float *s_u0 = lds + 64 * kRows, *s_kap = s_u0 + 64, *s_beta = s_kap + 64;
+    int *s_pub = reinterpret_cast<int *>(s_beta + 64);
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int rlo = lane * RPL;
+    const int64_t blk = blockIdx.x;
+    const int64_t r0 = part_start(part, blk);
+    const int rows = (int)(part_start(part, blk + 1) - r0);
+    nc = __builtin_amdgcn_readfirstlane(nc);
+    const int own = __builtin_amdgcn_readfirstlane(w * CPW);   // the wave's first column
+
+    float f[CPW][RPL];
+    const bool vec = own + CPW <= nc && (ldx & 3) == 0 && ((uintptr_t)X & 15) == 0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int r = rlo + i;
+        if (vec) {
+            float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+            if (r < rows) {
+                const float *xr = X + (r0 + r) * ldx + own;
+                a = *(const float4 *)xr;
+                b = *(const float4 *)(xr + 4);
+            }
+            f[0][i] = a.x, f[1][i] = a.y, f[2][i] = a.z, f[3][i] = a.w;
+            f[4][i] = b.x, f[5][i] = b.y, f[6][i] = b.z, f[7][i] = b.w;
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < CPW; ++cc)
+                f[cc][i] = (own + cc < nc && r < rows) ? X[(r0 + r) * ldx + own + cc] : 0.0f;
+        }
     }
+
+    // x_c -= kappa (u^T x_c) u for columns cc >= first (compile time) of the
+    // wave; the column sums go through wave_sum's steps side by side
+    auto apply = [&](const float (&u)[RPL], float kap, int first) {
+        float d[CPW];
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc) {
+            d[cc] = 0.0f;
+            if (cc < first)
+                continue;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                d[cc] = fmaf(u[i], f[cc][i], d[cc]);
+        }
+        wave_sums<CPW>(d, first);
+#pragma unroll
+        for (int cc = 0; cc < CPW; ++cc) {
+            if (cc < first)
+                continue;
+            const float sc = kap * d[cc];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                f[cc][i] = fmaf(-sc, u[i], f[cc][i]);
+        }
+    };
+
+    if (t == 0)
+        *s_pub = 0;
+    __syncthreads();
+    bool timed_out = false;
+    if (own < nc) {
+        // the reflections of the waves to the left, as they are published
+        for (int jv = 0; jv < own; ++jv) {
+            const int j = __builtin_amdgcn_readfirstlane(jv);
+            int spins = 0;
+            while (__hip_atomic_load(s_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <= j) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1 << 22)) {
+                    timed_out = true;
+                    break;
+                }
+            }
+            const float4 uv = *(const float4 *)&ubuf[j][rlo];
+            const float u[RPL] = {uv.x, uv.y, uv.z, uv.w};
+            apply(u, s_kap[j], 0);
+        }
+        // this wave's reflections
+#pragma unroll
+        for (int cj = 0; cj < CPW; ++cj) {
+            const int j = own + cj;
+            if (j >= nc)
+                break;
+            float o[RPL], s4 = 0.0f;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                o[i] = rlo + i < j ? 0.0f : f[cj][i];
+                s4 = fmaf(o[i], o[i], s4);
+            }
+            const float ss = wave_sum(s4);
+            // x_j: row j is entry j % 4 (= cj % 4) of lane j / 4
+            const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f[cj][cj & 3]),
+                                                                      j >> 2));
+            float u0 = 0.0f, kap = 0.0f, beta = 0.0f;   // a zero column needs no reflection
+            if (ss >= 0x1p-96f && ss <= 0x1p96f) {
+                const float nrm = sqrtf(ss);
+                beta = x0 >= 0.0f ? -nrm : nrm;
+                u0 = x0 - beta;
+                kap = 1.0f / (beta * (beta - x0));
+            } else {
+                double sd = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    sd = fma((double)o[i], (double)o[i], sd);
+                const double nrm = sqrt(wave_sum(sd));
+                if (nrm > 0.0) {
+                    const double bt = x0 >= 0.0f ? -nrm : nrm;
+                    u0 = (float)((double)x0 - bt);
+                    kap = (float)(1.0 / (bt * (bt - (double)x0)));
+                    beta = (float)bt;
+                }
+            }
+            if (rlo + (cj & 3) == j)
+                o[cj & 3] = u0;
+            *(float4 *)&ubuf[j][rlo] = make_float4(o[0], o[1], o[2], o[3]);
+            if (lane == 0) {
+                s_u0[j] = u0;
+                s_kap[j] = kap;
+                s_beta[j] = beta;
+            }
+            __hip_atomic_store(s_pub, j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            apply(o, kap, cj + 1);
+        }
+    }
+    __syncthreads();
+    if (timed_out)
+        f[0][0] = NAN;
+
+    float *Rb = R + blk * nc * ldr;
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc) {
+        const int c = own + cc;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int rr = rlo + i;
+            if (c < nc && rr < nc)
+                Rb[(int64_t)rr * ldr + c] = c > rr ? f[cc][i] : (c == rr ? s_beta[rr] : 0.0f);
+        }
+    }
+
+    float u0c[CPW];
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc)
+        u0c[cc] = own + cc < nc ? s_u0[own + cc] : 0.0f;
+    form_q64(
+        [&](float *Us) {
+#pragma unroll
+            for (int cc = 0; cc < CPW; ++cc) {
+                const int c = own + cc;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = rlo + i;
+                    const float v = (c >= nc || r < c) ? 0.0f : (r == c ? u0c[cc] : f[cc][i]);
+                    Us[r * 64 + (c ^ (r & 31))] = v;
+                }
+            }
+        },
+        nc, lane, w, rows, s_kap, lds, Q + r0 * ldq, ldq);
 }
 
 // out[r, :] = (in[r, :] - sub [r < nc] e_r^T) M_b for every row r < part.rows,
@@ -731,8 +936,12 @@ hipError_t tsqr_run_b(const float *A, int64_t lda, int nc, float *Q, int64_t ldq
         const int64_t ldo = l == 0 ? ldq : nc;
         float *ro = l == L ? R : buf(l + 1);
         const int64_t ldro = l == L ? ldr : nc;
-        hipLaunchKernelGGL(qr_block_kernel<B>, dim3(pl.nb), dim3(8 * B), 0, s, in, ldi, pl, nc,
-                           qo, ldo, ro, ldro);
+        if constexpr (B == 64)
+            hipLaunchKernelGGL(qr_block64_kernel, dim3(pl.nb), dim3(512), 0, s, in, ldi, pl, nc,
+                               qo, ldo, ro, ldro);
+        else
+            hipLaunchKernelGGL(qr_block_kernel<B>, dim3(pl.nb), dim3(8 * B), 0, s, in, ldi, pl,
+                               nc, qo, ldo, ro, ldro);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
