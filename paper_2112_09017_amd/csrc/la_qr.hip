@@ -228,11 +228,20 @@ __device__ __forceinline__ void form_q64(WriteU write_u, int nc, int lane, int w
     if (w < 3) {
         const int bi = w == 2 ? 1 : 0, bj = w == 0 ? 0 : 1;
         f32x16_t acc = {};
-        for (int k = 0; k < rows; k += 2) {
-            const int r = k + hk;
-            const float a = Us[r * 64 + ((bi * 32 + li) ^ (r & 31))];
-            const float b = Us[r * 64 + ((bj * 32 + li) ^ (r & 31))];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        // 16 rows per step, the loads ahead of the products (U is zero below
+        // the block's rows, so the padding adds exact zeros)
+        const int kend = (rows + 15) & ~15;
+        for (int k0 = 0; k0 < kend; k0 += 16) {
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int r = k0 + 2 * q + hk;
+                a[q] = Us[r * 64 + ((bi * 32 + li) ^ (r & 31))];
+                b[q] = Us[r * 64 + ((bj * 32 + li) ^ (r & 31))];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -271,11 +280,20 @@ __device__ __forceinline__ void form_q64(WriteU write_u, int nc, int lane, int w
         if (br * 32 >= rows)
             continue;
         f32x16_t acc = {};
-        for (int k = 0; k < nc; k += 2) {
-            const int kk = k + hk, r = br * 32 + li;
-            const float a = Us[r * 64 + (kk ^ (r & 31))];
-            const float b = SZ[kk * 64 + bc * 32 + li];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        // 16 columns of U per step, the loads ahead of the products (U's
+        // columns and Z's rows from nc on are zero)
+        const int kend = (nc + 15) & ~15;
+        for (int k0 = 0; k0 < kend; k0 += 16) {
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kk = k0 + 2 * q + hk, r = br * 32 + li;
+                a[q] = Us[r * 64 + (kk ^ (r & 31))];
+                b[q] = SZ[kk * 64 + bc * 32 + li];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
