@@ -195,20 +195,22 @@ __device__ inline double wave_sum(double v)
 // Q = H_0 ... H_{nc-1} [I; 0] of a block's 64-column reflector set, in
 // compact WY form: H_0 ... H_{nc-1} = I - U T U^T with U = [u_0 ... u_{nc-1}]
 // (u_j zero above row j) and T upper triangular, T^-1 = diag(1/kappa) +
-// N, N the strict upper part of S = U^T U.  So Q = [I; 0] - U Z with
-// Z = T U_top^T (U_top: the first 64 rows of U), and Z = diag(kappa)
-// (U_top^T - N Z), solved from the last row up without a division (a column
-// without a reflection, kappa = 0, gives a zero row of Z and of T).
+// N, N the strict upper part of S = U^T U; T = (I + diag(kappa) N)^-1
+// diag(kappa) needs no division (a column without a reflection, kappa = 0,
+// gives a zero row and column of T).  So Q = [I; 0] - U Z with Z = T U_top^T
+// (U_top: the first 64 rows of U).  With T in 32 x 32 blocks, T_LH =
+// -T_LL N_LH T_HH (two reflector sets joined).
 //   1. each lane writes its 32 entries of U (zero above the diagonal, u_j on
 //      it, the stored x below) to LDS, row r at r * 64, column j at slot
 //      j ^ (r & 31), so both a row and a column of 32 are conflict-free;
 //   2. three waves form the blocks (0,0), (0,1), (1,1) of S on the matrix
 //      cores (v_mfma_f32_32x32x2f32, K = the block's rows) and write S
 //      transposed (S[i][k] at k * 64 + i);
-//   3. wave 0 solves for Z, lane = column: once row k of Z is final it
-//      subtracts S[i][k] z_k from every row i < k, then writes row k over
-//      column k of S (no longer read);
-//   4. all eight waves form [I; 0] - U Z, 16 blocks of 32 x 32, on the matrix
+//   3. wave 0 forms T_LL and T_HH (lane = column), 32 steps each, side by
+//      side in the two halves of the wave;
+//   4. wave 1 forms T_LH on the matrix cores;
+//   5. four waves form Z = T U_top^T on the matrix cores;
+//   6. all eight waves form [I; 0] - U Z, 16 blocks of 32 x 32, on the matrix
 //      cores and write it to Q (rows of this block; ldq).
 // write_u(Us): stores this thread's entries of U (step 1), given the values it
 // read from LDS before the call (the space is reused); s_kap: kappa_j in LDS
@@ -250,15 +252,25 @@ __device__ __forceinline__ void form_q64(WriteU write_u, int nc, int lane, int w
         }
     }
     __syncthreads();
+    // 3. T_LL and T_HH, the diagonal 32 x 32 blocks of T, in one wave: lane
+    // c of half h solves (I + diag(kappa_h) N_hh) t = kappa_c e_c from the
+    // last row up without a division (t_k *= kappa_k once final, then
+    // t_i -= N[i][k] t_k for i < k), then stores row-major, column slot
+    // c ^ r, over the S block it has read
     if (w == 0) {
-        float z[64];
+        const int hf = lane >> 5, c = lane & 31;
+        float *sb = SZ + hf * (32 * 64 + 32);   // S[32 hf + i][32 hf + k] at sb[k * 64 + i]
+        float z[32];
 #pragma unroll
-        for (int i = 0; i < 64; ++i)
-            z[i] = Us[lane * 64 + (i ^ (lane & 31))];   // U_top^T (i, lane) = U (lane, i)
+        for (int i = 0; i < 32; ++i)
+            z[i] = i == c ? 1.0f : 0.0f;
 #pragma unroll
-        for (int k = 63; k >= 0; --k) {
-            z[k] *= __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kapl), k));
-            const float *sk = SZ + k * 64;              // S[0..k-1][k]
+        for (int k = 31; k >= 0; --k) {
+            const float klo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kapl), k));
+            const float khi =
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kapl), 32 + k));
+            z[k] *= hf ? khi : klo;
+            const float *sk = sb + k * 64;
 #pragma unroll
             for (int i = 0; i < (k & ~3); i += 4) {
                 const float4 sv = *reinterpret_cast<const float4 *>(sk + i);
@@ -270,8 +282,88 @@ __device__ __forceinline__ void form_q64(WriteU write_u, int nc, int lane, int w
 #pragma unroll
             for (int i = k & ~3; i < k; ++i)
                 z[i] = fmaf(-sk[i], z[k], z[i]);
-            SZ[k * 64 + lane] = z[k];                   // row k of Z
         }
+        // every lane's reads of the block before any lane's stores over it
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 32; ++r)
+            sb[r * 64 + (c ^ r)] = z[r];           // T_hh[r][c]
+    }
+    __syncthreads();
+    // 4. T_LH = -T_LL (N_LH T_HH) in one wave on the matrix cores: P =
+    // N_LH T_HH into the unused lower-left block (P[i][j] at i * 64 + 32 + j),
+    // then -T_LL P over N_LH (T_LH[i][j] at (32 + j) * 64 + i)
+    if (w == 1) {
+        f32x16_t acc = {};
+#pragma unroll
+        for (int k0 = 0; k0 < 32; k0 += 16) {
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kk = k0 + 2 * q + hk;
+                a[q] = SZ[(32 + kk) * 64 + li];                 // N_LH[li][kk]
+                b[q] = SZ[(32 + kk) * 64 + 32 + (li ^ kk)];     // T_HH[kk][li]
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            SZ[(8 * (e >> 2) + 4 * hk + (e & 3)) * 64 + 32 + li] = acc[e];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        f32x16_t acc2 = {};
+#pragma unroll
+        for (int k0 = 0; k0 < 32; k0 += 16) {
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kk = k0 + 2 * q + hk;
+                a[q] = SZ[li * 64 + (kk ^ li)];                 // T_LL[li][kk]
+                b[q] = SZ[kk * 64 + 32 + li];                   // P[kk][li]
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], acc2, 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            SZ[(32 + li) * 64 + 8 * (e >> 2) + 4 * hk + (e & 3)] = -acc2[e];
+    }
+    __syncthreads();
+    // 5. Z = T U_top^T, four 32 x 32 blocks on four waves (T_HL = 0), then Z
+    // row-major over T
+    f32x16_t zacc = {};
+    if (w < 4) {
+        const int bi = w >> 1, col = (w & 1) * 32 + li;
+#pragma unroll
+        for (int k0 = 0; k0 < 64; k0 += 16) {
+            if (k0 < 32 * bi)
+                continue;
+            float a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kk = k0 + 2 * q + hk;
+                if (bi == 1)
+                    a[q] = SZ[(32 + li) * 64 + 32 + ((kk - 32) ^ li)];   // T_HH[li][kk - 32]
+                else if (k0 < 32)
+                    a[q] = SZ[li * 64 + (kk ^ li)];                       // T_LL[li][kk]
+                else
+                    a[q] = SZ[kk * 64 + li];                              // T_LH[li][kk - 32]
+                b[q] = Us[col * 64 + (kk ^ (col & 31))];                  // U[col][kk]
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                zacc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], b[q], zacc, 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (w < 4) {
+        const int bi = w >> 1, col = (w & 1) * 32 + li;
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            SZ[(32 * bi + 8 * (e >> 2) + 4 * hk + (e & 3)) * 64 + col] = zacc[e];
     }
     __syncthreads();
 #pragma unroll
