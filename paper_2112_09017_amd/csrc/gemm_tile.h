@@ -671,7 +671,13 @@ __device__ __forceinline__ void tile_coords(const GemmDesc &d, int lin, int &tm,
 // tiles share 4 A and 8 B panels in its L2; consecutive rounds move down the
 // tile rows, keeping their B panels.  (With every XCD sweeping its own band of
 // tile rows across all columns instead, the packed kernel fetched 1.6 times as
-// much from HBM.)  Other tile counts, and Gram launches, use the general order.
+// much from HBM.)  A Gram launch over a whole upper triangle of 16k x 16k
+// tiles takes its off-diagonal 16 x 16 blocks the same way, column by column
+// (consecutive rounds keep their B panels), then the 136-tile triangles of the
+// diagonal blocks, each XCD a contiguous half of one (row by row in it); in
+// plain row order an XCD's 32 tiles would share one A panel and need 32 B
+// panels.  Other tile counts, and Gram launches over part of the triangle,
+// use the general order.
 __device__ __forceinline__ void round_tile_coords(const GemmDesc &d, int &tm, int &tn)
 {
     if (kXcds == 8 && d.tiles_m % 16 == 0 && d.tiles_n % 16 == 0 && !d.gram) {
@@ -680,6 +686,27 @@ __device__ __forceinline__ void round_tile_coords(const GemmDesc &d, int &tm, in
         const int sm = d.tiles_m / 16;
         tm = 16 * (r % sm) + 4 * (x % 4) + sl % 4;
         tn = 16 * (r / sm) + 8 * (x / 4) + sl / 4;
+    } else if (kXcds == 8 && d.gram && d.tiles_n % 16 == 0 &&
+               d.num_tiles == d.tiles_n * (d.tiles_n + 1) / 2) {
+        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+        const int nb = d.tiles_n / 16, noff = nb * (nb - 1) / 2;
+        if (i < 32 * noff) {
+            // off-diagonal block r: column C, row R < C
+            const int r = i / 32, sl = i % 32;
+            int C = 1;
+            while (C * (C + 1) / 2 <= r)
+                ++C;
+            const int R = r - C * (C - 1) / 2;
+            tm = 16 * R + 4 * (x % 4) + sl % 4;
+            tn = 16 * C + 8 * (x / 4) + sl / 4;
+        } else {
+            // diagonal blocks: 136 upper tiles each, 17 nb per XCD
+            const int g = x * (17 * nb) + (i - 32 * noff);
+            int lr, lc;
+            gram_tile(g % 136, 16, lr, lc);
+            tm = 16 * (g / 136) + lr;
+            tn = 16 * (g / 136) + lc;
+        }
     } else {
         tile_coords(d, xcd_remap(blockIdx.x, d.num_tiles), tm, tn);
     }
