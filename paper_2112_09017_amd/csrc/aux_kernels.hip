@@ -55,6 +55,12 @@ void gemm_finalize(GemmDesc &d, int prec)
         const int64_t large = d.gram ? ln * (ln + 1) / 2 : lm * ln;
         d.small = large < 128 ? 1 : 0;
     }
+    gemm_set_class(d, prec, d.small);
+}
+
+void gemm_set_class(GemmDesc &d, int prec, int small)
+{
+    d.small = small;
     const int bm = tile_m(prec, d.small), bn = tile_n(prec, d.small);
     d.tiles_m = (int)((d.M + bm - 1) / bm);
     d.tiles_n = (int)((d.N + bn - 1) / bn);

@@ -60,6 +60,9 @@ int tile_n(int prec, int small = 0);
 
 // Fills the derived fields (tile class, vec flags, tile counts) of d.
 void gemm_finalize(GemmDesc &d, int prec);
+// Sets d's tile class (small: 128 x 128, else the precision's large tiles)
+// and the tile counts that follow from it; the products are the same either way.
+void gemm_set_class(GemmDesc &d, int prec, int small);
 
 hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s);
 

@@ -416,7 +416,18 @@ struct HipExec {
                 e = launch_scale_by_norm(d->A, r->n, d->X[0], r->n, r->m, r->n, d->scal, stream);
             d->cur = 0;
         }
-        // 2. one step for every running request
+        // 2. one step for every running request.  A tick whose requests would
+        // fill the device twice over with large tiles runs all of them on large
+        // tiles (fewer operand re-reads per flop; the products are the same
+        // bits in either tile class); a lighter tick keeps each request's own
+        // choice, which favours small tiles for a lone mid-size request.
+        int64_t large_load = 0;
+        for (serve::Req *r : run) {
+            const int pr = r->step_prec();
+            large_load += (int64_t)((r->m + tile_m(pr, 0) - 1) / tile_m(pr, 0)) *
+                          ((r->n + tile_n(pr, 0) - 1) / tile_n(pr, 0));
+        }
+        const bool all_large = large_load >= 2 * (int64_t)ctx->num_cus;
         std::vector<Launch> grams, updates;
         std::vector<ReduceItem> red;
         double *dev_d = (double *)(stage_dev + kDescBytes + kItemBytes);
@@ -427,10 +438,14 @@ struct HipExec {
             const PolarPlan &p = r->plan;
             const bool pre = r->precond();
             const int prec = r->step_prec();
-            add_problem(grams, prec, 0, 0,
-                        gram_desc(d->X[d->cur], d->X[d->cur], d->P, r->m, r->n,
-                                  pre ? (float)(-p.c) : -1.0f, 1.0f, 0, prec));
+            GemmDesc gd = gram_desc(d->X[d->cur], d->X[d->cur], d->P, r->m, r->n,
+                                    pre ? (float)(-p.c) : -1.0f, 1.0f, 0, prec);
             GemmDesc ud = update_desc(d->X[d->cur], d->P, d->X[d->cur ^ 1], r->m, r->n, prec);
+            if (all_large) {
+                gemm_set_class(gd, prec, 0);
+                gemm_set_class(ud, prec, 0);
+            }
+            add_problem(grams, prec, 0, 0, gd);
             if (pre) {
                 ud.alpha = (float)p.a;
             } else {

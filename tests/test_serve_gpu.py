@@ -145,6 +145,33 @@ def test_large_tile_requests_mix_equals_alone(la):
         assert orth <= TOL and resid <= TOL and dh <= TOL
 
 
+def test_busy_tick_large_tiles_equal_alone(la):
+    """Seven 2304 x 2304 requests in flight need 7 x 81 = 567 large tiles, more
+    than twice the CUs, so their ticks run every product on 256 x 256 tiles; one
+    of them served alone takes 128 x 128 tiles (81 large ones would leave most
+    CUs idle).  The tile class must not change a bit."""
+    import torch
+    cs = [la_inputs.polar_case_torch(2304, 2304, 10.0 ** -(2 + i % 4), (1000 + 3 * i, 1001 + 3 * i,
+                                                                       1002 + 3 * i))
+          for i in range(7)]
+    torch.cuda.empty_cache()
+    with la.Server(4 << 30, max_slots=16) as srv:
+        ids = [srv.submit(c[0]) for c in cs]
+        mix = wait_all(srv, ids, timeout=300)
+    for k in (0, 6):
+        A, _, s, V = cs[k]
+        with la.Server(4 << 30) as alone:
+            j = alone.submit(A)
+            s2, U2, H2, info2 = wait_all(alone, [j], timeout=300)[j]
+        status, U, H, info = mix[ids[k]]
+        assert status == s2 == la.Status.OK
+        assert np.array_equal(U, U2) and np.array_equal(H, H2)
+        assert info == info2
+        orth, resid, dh = fp64_checks(A, U, H, V, s)
+        print(k, info, f"orth={orth:.2e} resid={resid:.2e} dH={dh:.2e}")
+        assert orth <= TOL and resid <= TOL and dh <= TOL
+
+
 def test_tight_arena_admission(la):
     """An arena that holds two 512 x 512 requests at a time still serves six."""
     cs = [la_inputs.polar_case(512, 512, 1e-3, seeds=(930 + i, 940 + i, 950 + i))
