@@ -1,6 +1,6 @@
 """la_polar on the GPU against the FP64 oracle (Algorithm NS_Polar).
 
-Tolerances (the benchmark spec): ||U^T U - I||_F / sqrt(N) <= 1e-5 and
+Tolerances of the polar factors: ||U^T U - I||_F / sqrt(N) <= 1e-5 and
 ||A - U H||_F / ||A||_F <= 1e-5.  Derived here:
   * H is well conditioned (perturbation of H is bounded by about sqrt(2)
     times that of A), so ||H - H_oracle||_F / ||A||_F <= 1e-5;
