@@ -140,6 +140,21 @@ __device__ inline float wave_sum(float v)
     v += bcast_f32<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+// Maximum over the 64 lanes of a wave of an unsigned key, wave-uniform: the
+// DPP steps of wave_sum with max in place of the sum (keys are >= 0, so the
+// zeros that the masked broadcast rows read change nothing).
+__device__ inline unsigned wave_max(unsigned v)
+{
+    auto mx = [](unsigned a, unsigned b) { return a > b ? a : b; };
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true));
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true));
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, true));
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, true));
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, true));
+    v = mx(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, true));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // wave_sum of v[first .. N - 1], the N - first sums step by step side by side
 // (each step a DPP add: the moves read zero outside their rows)
 template <int CTRL, int ROWS = 0xF>
@@ -911,10 +926,7 @@ __global__ __launch_bounds__(512) void wy_inverse_kernel(const float *__restrict
                 key = kk > key ? kk : key;
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned o = (unsigned)__shfl_xor((int)key, off);
-            key = o > key ? o : key;
-        }
+        key = wave_max(key);
         const int p = __builtin_amdgcn_readfirstlane(127 - (int)(key & 0x7Fu));
 #pragma unroll
         for (int q = 0; q < RL; ++q)
