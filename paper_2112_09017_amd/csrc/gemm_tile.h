@@ -1094,7 +1094,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>()))
 }
 
 // Persistent grouped kernel: workgroup b runs items b, b + grid, ...; each
-// item is one tile of one problem, computed exactly as gemm_kernel would.
+// item is one tile of one problem, computed exactly as gemm_kernel would.  A
+// capped grid leaves CUs to work on other streams (the panel chain of CAQR).
 template <int PREC, bool AKC, bool BKC>
 __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
     gemm_grouped_kernel(const GemmDesc *__restrict__ probs, const GroupItem *__restrict__ items,
@@ -1110,6 +1111,26 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
         gemm_tile<PREC, AKC, BKC, true>(d, tm, tn, smem, red);
         __syncthreads();
     }
+}
+
+// Grouped kernel, one workgroup per item: workgroup b computes item b exactly
+// as gemm_kernel would (the same loop, so the same bits as the persistent
+// kernel too); the items are dispatched in the order they are staged in.
+template <int PREC, bool AKC, bool BKC>
+__global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>()))
+    gemm_items_kernel(const GemmDesc *__restrict__ probs, const GroupItem *__restrict__ items,
+                      int num_items)
+{
+    __shared__ __attribute__((aligned(16))) char smem[2 * Geo<PREC>::stage_bytes];
+    __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
+    const int it = blockIdx.x;
+    if (it >= num_items)
+        return;
+    const GroupItem gi = items[it];
+    const GemmDesc d = probs[gi.prob];
+    int tm, tn;
+    tile_coords(d, gi.tile, tm, tn);
+    gemm_tile<PREC, AKC, BKC>(d, tm, tn, smem, red);
 }
 
 // ---------------------------------------------------------------- packed operands
@@ -1523,24 +1544,35 @@ hipError_t launch_t(const GemmDesc &d, hipStream_t s)
 }
 
 // grid_size is the number of CUs; small tiles run two workgroups per CU.
+template <int PREC, bool AKC, bool BKC>
+void launch_grouped_kern(bool persist, dim3 grid, dim3 block, hipStream_t s,
+                         const GemmDesc *probs, const GroupItem *items, int num_items)
+{
+    if (persist)
+        hipLaunchKernelGGL((gemm_grouped_kernel<PREC, AKC, BKC>), grid, block, 0, s, probs,
+                           items, num_items);
+    else
+        hipLaunchKernelGGL((gemm_items_kernel<PREC, AKC, BKC>), grid, block, 0, s, probs, items,
+                           num_items);
+}
+
 template <int PREC>
 hipError_t launch_grouped_one(int akc, int bkc, const GemmDesc *probs, const GroupItem *items,
                               int num_items, int grid_size, hipStream_t s)
 {
+    // grid_size > 0: persistent workgroups, at most grid_size per GOCC; else
+    // one workgroup per item
+    const bool persist = grid_size > 0;
     grid_size *= Cfg<PREC>::GOCC;
-    dim3 grid(grid_size < num_items ? grid_size : num_items), block(Geo<PREC>::NT);
+    dim3 grid(persist && grid_size < num_items ? grid_size : num_items), block(Geo<PREC>::NT);
     if (akc && bkc)
-        hipLaunchKernelGGL((gemm_grouped_kernel<PREC, true, true>), grid, block, 0, s, probs,
-                           items, num_items);
+        launch_grouped_kern<PREC, true, true>(persist, grid, block, s, probs, items, num_items);
     else if (akc)
-        hipLaunchKernelGGL((gemm_grouped_kernel<PREC, true, false>), grid, block, 0, s, probs,
-                           items, num_items);
+        launch_grouped_kern<PREC, true, false>(persist, grid, block, s, probs, items, num_items);
     else if (bkc)
-        hipLaunchKernelGGL((gemm_grouped_kernel<PREC, false, true>), grid, block, 0, s, probs,
-                           items, num_items);
+        launch_grouped_kern<PREC, false, true>(persist, grid, block, s, probs, items, num_items);
     else
-        hipLaunchKernelGGL((gemm_grouped_kernel<PREC, false, false>), grid, block, 0, s, probs,
-                           items, num_items);
+        launch_grouped_kern<PREC, false, false>(persist, grid, block, s, probs, items, num_items);
     return hipGetLastError();
 }
 

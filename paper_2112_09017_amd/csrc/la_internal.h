@@ -68,6 +68,9 @@ hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s);
 
 // Grouped launch: every item is one output tile of one problem; all problems
 // share precision and operand layouts.  probs / items live in device memory.
+// grid_size > 0: that many persistent workgroups per CU-occupancy slot at
+// most (the items loop over them, leaving CUs to other streams); 0: one
+// workgroup per item.  The results are the same bits either way.
 struct GroupItem {
     int prob;
     int tile;   // linear tile index within the problem

@@ -388,7 +388,7 @@ struct HipExec {
             const Launch &L = *st[i].L;
             hipStream_t s = i == 0 ? stream : side[(i - 1) % kSide];
             e = launch_gemm_grouped(L.prec, L.akc, L.bkc, L.small, st[i].dd, st[i].di,
-                                    (int)L.items.size(), ctx->num_cus, s);
+                                    (int)L.items.size(), 0, s);
         }
         for (int k = 0; k < used && e == hipSuccess; ++k) {
             e = hipEventRecord(ev_side[k], side[k]);
