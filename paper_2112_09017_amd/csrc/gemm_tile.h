@@ -40,9 +40,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.
-constexpr int kXcds = 8;
-
 // s_waitcnt immediate (gfx9 encoding) that waits for vmcnt == 0 only:
 // vmcnt bits [3:0] and [15:14] zero, expcnt [6:4] and lgkmcnt [11:8] at their
 // maxima (no wait).
@@ -205,6 +202,20 @@ __device__ __forceinline__ int frag_off(int t, int frow, int fk, int lane)
 
 // ---------------------------------------------------------------- loader
 
+// p as a pointer to global (device) memory.  Operands and outputs are read and
+// written through such pointers, so the accesses are global instructions even
+// where the compiler cannot see that a pointer is global (a descriptor the
+// grouped kernels read from memory): flat accesses would also count against
+// the LDS counter, and every wait for a stage's LDS reads would then wait for
+// the next stage's operand loads in flight as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+typedef const __attribute__((address_space(1))) f32x4 gf32x4;
+typedef const __attribute__((address_space(1))) f32x2 gf32x2;
+
 // Loads one K stage of op(X) rows [r0, r0+ROWS) x k [k0, k0+BK) into
 // registers.  KC: k is contiguous in memory (X[r * ld + k]); otherwise the
 // row index is (X[k * ld + r]).  Work unit = 8 k x R rows: R float4 pairs
@@ -261,8 +272,8 @@ struct Loader {
             if constexpr (KC) {
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    const f32x4 *p = reinterpret_cast<const f32x4 *>(
-                        base + off[u] + (int64_t)q * (ROWS / R) * ld);
+                    gf32x4 *p = reinterpret_cast<gf32x4 *>(
+                        gmem(base) + off[u] + (int64_t)q * (ROWS / R) * ld);
                     const f32x4 a = p[0], b = p[1];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
@@ -273,14 +284,14 @@ struct Loader {
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const float *p = base + off[u] + (int64_t)j * ld;
+                    const auto p = gmem(base) + off[u] + (int64_t)j * ld;
                     if constexpr (R == 4) {
-                        const f32x4 a = *reinterpret_cast<const f32x4 *>(p);
+                        const f32x4 a = *reinterpret_cast<gf32x4 *>(p);
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
                             v[u][q][j] = a[q];
                     } else if constexpr (R == 2) {
-                        const f32x2 a = *reinterpret_cast<const f32x2 *>(p);
+                        const f32x2 a = *reinterpret_cast<gf32x2 *>(p);
                         v[u][0][j] = a[0];
                         v[u][1][j] = a[1];
                     } else {
@@ -295,6 +306,7 @@ struct Loader {
                                                  int64_t Rn, int64_t K, int64_t r0, int64_t k0)
     {
         const int t = threadIdx.x;
+        const auto gX = gmem(X);
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
             const int uid = t + u * NT;
@@ -307,7 +319,7 @@ struct Loader {
                     const int64_t gk = k0 + 8 * k8 + j;
                     float x = 0.0f;
                     if (gr < Rn && gk < K)
-                        x = KC ? X[gr * ld + gk] : X[gk * ld + gr];
+                        x = KC ? gX[gr * ld + gk] : gX[gk * ld + gr];
                     v[u][q][j] = x;
                 }
             }
@@ -743,7 +755,7 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
                 for (int e = 0; e < 16; ++e) {
                     int64_t row = rb + i * 32 + (e >> 2) * 8 + (e & 3);
                     row = row < d.M ? row : d.M - 1;
-                    ev[e] = d.E[row * d.lde + cc];
+                    ev[e] = gmem(d.E)[row * d.lde + cc];
                 }
                 __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             }
@@ -760,9 +772,9 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
                 }
                 if (row == col)
                     val = val + d.gamma;
-                d.C[row * d.ldc + col] = val;
+                gmem(d.C)[row * d.ldc + col] = val;
                 if (d.gram && !d.gram_upper && row != col)
-                    d.C[col * d.ldc + row] = val;
+                    gmem(d.C)[col * d.ldc + row] = val;
                 if (want_ss) {
                     const double df = (double)val - (double)evv;
                     ss += df * df;
@@ -781,7 +793,7 @@ __device__ __forceinline__ void epilogue(const GemmDesc &d,
             double s = 0.0;
             for (int k = 0; k < Cfg<PREC>::WM * Cfg<PREC>::WN; ++k)
                 s += red[k];
-            d.partials[(int64_t)tm * d.tiles_n + tn] = s;
+            gmem(d.partials)[(int64_t)tm * d.tiles_n + tn] = s;
         }
     }
 }
@@ -1105,6 +1117,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
     __shared__ double red[Cfg<PREC>::WM * Cfg<PREC>::WN];
     for (int it = blockIdx.x; it < num_items; it += gridDim.x) {
         const GroupItem gi = items[it];
+        if (gi.prob < 0)
+            continue;   // empty item (uniform over the workgroup)
         const GemmDesc d = probs[gi.prob];
         int tm, tn;
         tile_coords(d, gi.tile, tm, tn);
@@ -1115,7 +1129,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, Cfg<PREC>::GOCC)
 
 // Grouped kernel, one workgroup per item: workgroup b computes item b exactly
 // as gemm_kernel would (the same loop, so the same bits as the persistent
-// kernel too); the items are dispatched in the order they are staged in.
+// kernel too); workgroup b runs on XCD b % kXcds, so the caller places the
+// items on the XCDs by their position in the list.
 template <int PREC, bool AKC, bool BKC>
 __global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>()))
     gemm_items_kernel(const GemmDesc *__restrict__ probs, const GroupItem *__restrict__ items,
@@ -1127,6 +1142,8 @@ __global__ void __launch_bounds__(Geo<PREC>::NT, (kernel_occ<PREC, AKC, BKC>()))
     if (it >= num_items)
         return;
     const GroupItem gi = items[it];
+    if (gi.prob < 0)
+        return;   // empty item
     const GemmDesc d = probs[gi.prob];
     int tm, tn;
     tile_coords(d, gi.tile, tm, tn);

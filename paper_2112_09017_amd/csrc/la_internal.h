@@ -66,11 +66,16 @@ void gemm_set_class(GemmDesc &d, int prec, int small);
 
 hipError_t launch_gemm(int prec, const GemmDesc &d, hipStream_t s);
 
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs.
+constexpr int kXcds = 8;
+
 // Grouped launch: every item is one output tile of one problem; all problems
 // share precision and operand layouts.  probs / items live in device memory.
 // grid_size > 0: that many persistent workgroups per CU-occupancy slot at
 // most (the items loop over them, leaving CUs to other streams); 0: one
-// workgroup per item.  The results are the same bits either way.
+// workgroup per item, item b on workgroup b, hence on XCD b % kXcds.  The
+// results are the same bits either way.  An item with prob < 0 is empty
+// (padding of a list laid out for the XCDs).
 struct GroupItem {
     int prob;
     int tile;   // linear tile index within the problem

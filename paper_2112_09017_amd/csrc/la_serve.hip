@@ -204,6 +204,21 @@ GemmDesc update_desc(const float *X, const float *P, float *Xn, int64_t m, int64
     return d;
 }
 
+// Lays out a launch's items for the per-item grouped kernel (item b runs on
+// XCD b % kXcds; serve::xcd_layout); empty items pad the XCD lists.
+void xcd_order(Launch &L)
+{
+    std::vector<int64_t> tiles, cost;
+    for (const GemmDesc &d : L.probs) {
+        tiles.push_back(d.num_tiles);
+        cost.push_back(d.K);
+    }
+    const std::vector<serve::Slot> lay = serve::xcd_layout(tiles, cost, kXcds);
+    L.items.resize(lay.size());
+    for (size_t i = 0; i < lay.size(); ++i)
+        L.items[i] = GroupItem{lay[i].prob, lay[i].tile};
+}
+
 struct HipExec {
     la_context *ctx = nullptr;
     int device = 0;
@@ -229,7 +244,8 @@ struct HipExec {
     // descriptors and tile items one tick stages for r: a Gram and an update,
     // at the most demanding precision the request may step at (H, staged after
     // the tick's wait, needs no more: two descriptors and twice the Gram's
-    // tiles, at most the update's)
+    // tiles, at most the update's), plus the empty items that pad the XCD
+    // lists (fewer than kXcds per problem)
     void stage_need(const serve::Req &r, size_t *descs, size_t *items)
     {
         size_t it = 0;
@@ -244,7 +260,7 @@ struct HipExec {
         const GemmDesc h = gram_desc(nullptr, nullptr, nullptr, r.m, r.n, 1.0f, 0.0f, 1,
                                      r.plan.prec_h);
         *descs = 2;
-        *items = std::max(it, 2 * (size_t)h.num_tiles);
+        *items = std::max(it, 2 * (size_t)h.num_tiles) + 2 * (kXcds - 1);
     }
     size_t desc_capacity() { return (kDescBytes - kMaxGroups * kAlign) / sizeof(GemmDesc); }
     size_t item_capacity() { return (kItemBytes - kMaxGroups * kAlign) / sizeof(GroupItem); }
@@ -331,20 +347,16 @@ struct HipExec {
     }
 
     // Stage each launch's descriptors and items in the pinned mirror of the
-    // reserved area (descriptors from dpos, items from ipos); items are
-    // ordered by decreasing K so the persistent workgroups share the work
-    // evenly.  Admission keeps a tick's staging within the area; the check
-    // here only guards that bound.
+    // reserved area (descriptors from dpos, items from ipos), the items laid
+    // out for the XCDs (xcd_order).  Admission keeps a tick's staging within
+    // the area; the check here only guards that bound.
     hipError_t stage(std::vector<Launch> &ls, size_t &dpos, size_t &ipos,
                      std::vector<Staged> &out)
     {
         for (auto &L : ls) {
             if (L.items.empty())
                 continue;
-            std::stable_sort(L.items.begin(), L.items.end(),
-                             [&](const GroupItem &x, const GroupItem &y) {
-                                 return L.probs[x.prob].K > L.probs[y.prob].K;
-                             });
+            xcd_order(L);
             const size_t db = L.probs.size() * sizeof(GemmDesc);
             const size_t ib = L.items.size() * sizeof(GroupItem);
             if (dpos + db > kDescBytes || ipos + ib > kItemBytes)

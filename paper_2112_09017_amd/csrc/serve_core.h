@@ -62,6 +62,60 @@ inline double now_s()
         .count();
 }
 
+// One entry of a grouped launch's item list: a tile of a problem, or empty
+// (prob < 0).
+struct Slot {
+    int prob;
+    int tile;
+};
+
+// Item list of a grouped launch for a device that deals workgroups to its
+// XCDs in turn (workgroup b to XCD b % xcds, each XCD with its own L2): entry
+// xcds i + x is the i-th item of XCD x.  Problem p has tiles[p] tiles (in
+// linear order, neighbours sharing operand panels) of cost[p] each (its K).
+// Every problem's tiles are cut into xcds contiguous runs, one per XCD, so
+// each XCD holds an equal share of every problem and neighbouring tiles meet
+// in one L2 (in plain order the tiles in flight on an XCD were every xcds-th
+// tile of a problem); the runs one tile longer go to the XCDs with the least
+// work so far, and an XCD takes the problems in order of decreasing cost.  The
+// lists are padded to one length with empty entries: fewer than xcds per
+// problem.
+inline std::vector<Slot> xcd_layout(const std::vector<int64_t> &tiles,
+                                    const std::vector<int64_t> &cost, int xcds)
+{
+    const int np = (int)tiles.size();
+    std::vector<int> byk(np);
+    for (int p = 0; p < np; ++p)
+        byk[p] = p;
+    std::stable_sort(byk.begin(), byk.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<std::vector<Slot>> lists(xcds);
+    std::vector<double> load(xcds, 0.0);
+    std::vector<int> ord(xcds);
+    std::vector<int64_t> len(xcds);
+    for (int p : byk) {
+        const int64_t q = tiles[p] / xcds, r = tiles[p] % xcds;
+        for (int x = 0; x < xcds; ++x)
+            ord[x] = x;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return load[x] < load[y]; });
+        for (int j = 0; j < xcds; ++j)
+            len[ord[j]] = q + (j < r ? 1 : 0);
+        int t = 0;
+        for (int x = 0; x < xcds; ++x) {
+            for (int64_t k = 0; k < len[x]; ++k)
+                lists[x].push_back(Slot{p, t++});
+            load[x] += (double)len[x] * (double)cost[p];
+        }
+    }
+    size_t longest = 0;
+    for (const auto &l : lists)
+        longest = std::max(longest, l.size());
+    std::vector<Slot> out(longest * xcds, Slot{-1, 0});
+    for (int x = 0; x < xcds; ++x)
+        for (size_t i = 0; i < lists[x].size(); ++i)
+            out[i * xcds + x] = lists[x][i];
+    return out;
+}
+
 // First-fit allocator over [lo, hi) with coalescing of freed blocks.
 class Arena {
   public:

@@ -802,6 +802,57 @@ static void test_bands_device_error()
     printf("bands_device_error: ok\n");
 }
 
+// The XCD layout of a grouped launch: every tile of every problem exactly
+// once, each XCD's share of a problem one contiguous run in tile order,
+// fewer than xcds empty entries per problem, and the work (tiles x cost) of
+// the XCDs within one tile of the largest cost of each other.
+static void test_xcd_layout()
+{
+    const int X = 8;
+    std::vector<std::vector<int64_t>> tiles_cases = {
+        {256}, {136}, {3}, {1024, 16, 10, 3, 1}, {7, 7, 7, 7, 7, 7, 7}, {}, {9, 200, 64}};
+    std::vector<std::vector<int64_t>> cost_cases = {
+        {2048}, {2048}, {128}, {4096, 512, 512, 256, 128}, {64, 64, 64, 64, 64, 64, 64}, {},
+        {1024, 2048, 512}};
+    for (size_t c = 0; c < tiles_cases.size(); ++c) {
+        const auto &tl = tiles_cases[c];
+        const auto &co = cost_cases[c];
+        const std::vector<Slot> lay = xcd_layout(tl, co, X);
+        CHECK(lay.size() % X == 0);
+        int64_t total = 0;
+        for (int64_t t : tl)
+            total += t;
+        CHECK((int64_t)lay.size() <= total + (int64_t)(X - 1) * (int64_t)tl.size());
+        std::vector<std::vector<int>> seen(tl.size());
+        for (size_t p = 0; p < tl.size(); ++p)
+            seen[p].assign(tl[p], 0);
+        std::vector<double> work(X, 0.0);
+        // per XCD and problem: the tiles in list order
+        std::vector<std::vector<std::vector<int>>> run(X, std::vector<std::vector<int>>(tl.size()));
+        for (size_t i = 0; i < lay.size(); ++i) {
+            const Slot s = lay[i];
+            if (s.prob < 0)
+                continue;
+            CHECK(s.prob < (int)tl.size() && s.tile >= 0 && s.tile < tl[s.prob]);
+            seen[s.prob][s.tile]++;
+            work[i % X] += (double)co[s.prob];
+            run[i % X][s.prob].push_back(s.tile);
+        }
+        for (size_t p = 0; p < tl.size(); ++p)
+            for (int v : seen[p])
+                CHECK(v == 1);
+        for (int x = 0; x < X; ++x)
+            for (size_t p = 0; p < tl.size(); ++p)
+                for (size_t k = 1; k < run[x][p].size(); ++k)
+                    CHECK(run[x][p][k] == run[x][p][k - 1] + 1);
+        if (!tl.empty()) {
+            const double mx = *std::max_element(work.begin(), work.end());
+            const double mn = *std::min_element(work.begin(), work.end());
+            CHECK(mx - mn <= (double)*std::max_element(co.begin(), co.end()));
+        }
+    }
+}
+
 int main(int argc, char **argv)
 {
     test_mix_and_counts();
@@ -814,6 +865,7 @@ int main(int argc, char **argv)
     test_bands_tick_independently();
     test_bands_keep_submission_order();
     test_bands_device_error();
+    test_xcd_layout();
     if (g_fail) {
         fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;
