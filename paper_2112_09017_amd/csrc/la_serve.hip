@@ -17,9 +17,9 @@
 //      a_def-RogueMatrix, or a Newton-Schulz step, eq. NewtonSchulz): one
 //      grouped Gram launch and one grouped update launch per precision and
 //      tile class cover all of them, whatever their sizes; the tick's
-//      descriptors and tile items go up in two copies, and the launches of a
-//      phase run side by side on up to four streams (a launch of a few
-//      large-tile problems fills only part of the device);
+//      descriptors, tile items and reduce items go up in one copy, and the
+//      launches of a phase run side by side on up to four streams (a launch
+//      of a few large-tile problems fills only part of the device);
 //   3. reduces the new requests' norms and the Newton-Schulz step norms in one
 //      grouped launch and reads them back in one copy: the tick's one wait;
 //   4. applies each request's stop test on the host; finished requests get
@@ -51,20 +51,26 @@ namespace la {
 namespace {
 
 constexpr size_t kAlign = 256;
-// Staging area of one band; kMaxBands of them at the start of the arena.
-constexpr size_t kDescBytes = 512u << 10;    // GemmDesc arrays of one staging pass
-constexpr size_t kItemBytes = 3u << 20;      // GroupItem arrays of one staging pass
-constexpr size_t kRedBytes = 512u << 10;     // ReduceItem array + norms read back
-constexpr size_t kBandReserve = kDescBytes + kItemBytes + kRedBytes;
+// Staging area of one band; kMaxBands of them at the start of the arena.  A
+// staging pass fills its upload region from the start, each launch's
+// descriptors followed by its items, then the tick's reduce items, so one copy
+// takes them all up; the region is sized as a descriptor budget plus an item
+// budget (admission counts both per request).
+constexpr size_t kDescBytes = 512u << 10;    // descriptor (and reduce item) budget
+constexpr size_t kItemBytes = 3u << 20;      // GroupItem budget
+constexpr size_t kUpBytes = kDescBytes + kItemBytes;
+constexpr size_t kRedBytes = 512u << 10;     // norms read back
+constexpr size_t kBandReserve = kUpBytes + kRedBytes;
 constexpr int kMaxSlots = 4096;
 // Size bands: square requests up to n = 2048 (m n^2 <= 2048^3) tick apart
 // from larger ones.
 constexpr int kMaxBands = 2;
 constexpr double kBandWork = 2048.0 * 2048.0 * 2048.0;
 // launch groups of one staging pass: 3 precisions x 2 tile classes x 2 phases,
-// each padded to kAlign
+// each with its descriptors and its items padded to kAlign
 constexpr int kMaxGroups = 12;
-constexpr size_t kRedItemsOff = 2 * kMaxSlots * sizeof(double);   // after the norms
+static_assert(2 * kMaxSlots * sizeof(double) <= kRedBytes, "norms of one tick");
+static_assert(2 * sizeof(ReduceItem) <= sizeof(GemmDesc), "reduce items in a descriptor slot");
 
 size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -245,7 +251,8 @@ struct HipExec {
     // at the most demanding precision the request may step at (H, staged after
     // the tick's wait, needs no more: two descriptors and twice the Gram's
     // tiles, at most the update's), plus the empty items that pad the XCD
-    // lists (fewer than kXcds per problem)
+    // lists (fewer than kXcds per problem), plus one descriptor's bytes for
+    // its reduce items (its norm when new, its step norm: at most two)
     void stage_need(const serve::Req &r, size_t *descs, size_t *items)
     {
         size_t it = 0;
@@ -259,9 +266,10 @@ struct HipExec {
         }
         const GemmDesc h = gram_desc(nullptr, nullptr, nullptr, r.m, r.n, 1.0f, 0.0f, 1,
                                      r.plan.prec_h);
-        *descs = 2;
+        *descs = 3;
         *items = std::max(it, 2 * (size_t)h.num_tiles) + 2 * (kXcds - 1);
     }
+    // each budget keeps room for the kAlign padding of kMaxGroups launches
     size_t desc_capacity() { return (kDescBytes - kMaxGroups * kAlign) / sizeof(GemmDesc); }
     size_t item_capacity() { return (kItemBytes - kMaxGroups * kAlign) / sizeof(GroupItem); }
 
@@ -346,12 +354,11 @@ struct HipExec {
             memcpy(H, d->hh, (size_t)r.n * r.n * 4);
     }
 
-    // Stage each launch's descriptors and items in the pinned mirror of the
-    // reserved area (descriptors from dpos, items from ipos), the items laid
-    // out for the XCDs (xcd_order).  Admission keeps a tick's staging within
-    // the area; the check here only guards that bound.
-    hipError_t stage(std::vector<Launch> &ls, size_t &dpos, size_t &ipos,
-                     std::vector<Staged> &out)
+    // Stage each launch's descriptors, then its items (laid out for the XCDs,
+    // xcd_order), in the pinned mirror of the upload region from pos on.
+    // Admission keeps a tick's staging within the region; the check here only
+    // guards that bound.
+    hipError_t stage(std::vector<Launch> &ls, size_t &pos, std::vector<Staged> &out)
     {
         for (auto &L : ls) {
             if (L.items.empty())
@@ -359,28 +366,22 @@ struct HipExec {
             xcd_order(L);
             const size_t db = L.probs.size() * sizeof(GemmDesc);
             const size_t ib = L.items.size() * sizeof(GroupItem);
-            if (dpos + db > kDescBytes || ipos + ib > kItemBytes)
+            if (pos + up(db) + ib > kUpBytes)
                 return hipErrorOutOfMemory;
-            memcpy(h_stage + dpos, L.probs.data(), db);
-            memcpy(h_stage + kDescBytes + ipos, L.items.data(), ib);
-            out.push_back(Staged{&L, (const GemmDesc *)(stage_dev + dpos),
-                                 (const GroupItem *)(stage_dev + kDescBytes + ipos)});
-            dpos += up(db);
-            ipos += up(ib);
+            memcpy(h_stage + pos, L.probs.data(), db);
+            memcpy(h_stage + pos + up(db), L.items.data(), ib);
+            out.push_back(Staged{&L, (const GemmDesc *)(stage_dev + pos),
+                                 (const GroupItem *)(stage_dev + pos + up(db))});
+            pos += up(db) + up(ib);
         }
         return hipSuccess;
     }
 
-    // One copy for all staged descriptors and one for all staged items.
-    hipError_t upload(size_t dpos, size_t ipos)
+    // One copy for everything staged.
+    hipError_t upload(size_t pos)
     {
-        hipError_t e = hipSuccess;
-        if (dpos)
-            e = hipMemcpyAsync(stage_dev, h_stage, dpos, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess && ipos)
-            e = hipMemcpyAsync(stage_dev + kDescBytes, h_stage + kDescBytes, ipos,
-                               hipMemcpyHostToDevice, stream);
-        return e;
+        return pos ? hipMemcpyAsync(stage_dev, h_stage, pos, hipMemcpyHostToDevice, stream)
+                   : hipSuccess;
     }
 
     // The launches of one phase side by side: the first on the executor's
@@ -442,7 +443,7 @@ struct HipExec {
         const bool all_large = large_load >= 2 * (int64_t)ctx->num_cus;
         std::vector<Launch> grams, updates;
         std::vector<ReduceItem> red;
-        double *dev_d = (double *)(stage_dev + kDescBytes + kItemBytes);
+        double *dev_d = (double *)(stage_dev + kUpBytes);
         for (serve::Req *r : fresh)
             red.push_back(ReduceItem{((DevReq *)r->x)->scal, 1, dev_d + red.size()});
         for (serve::Req *r : run) {
@@ -471,28 +472,29 @@ struct HipExec {
             }
             add_problem(updates, prec, 1, 0, ud);
         }
-        size_t dpos = 0, ipos = 0;
+        size_t pos = 0;
         std::vector<Staged> sg, su;
         if (e == hipSuccess)
-            e = stage(grams, dpos, ipos, sg);
+            e = stage(grams, pos, sg);
         if (e == hipSuccess)
-            e = stage(updates, dpos, ipos, su);
-        if (e == hipSuccess)
-            e = upload(dpos, ipos);
+            e = stage(updates, pos, su);
+        // the reduce items go up with the launches' descriptors and items
+        const ReduceItem *dev_ri = (const ReduceItem *)(stage_dev + pos);
+        const size_t rb = red.size() * sizeof(ReduceItem);
+        if (e == hipSuccess && pos + rb > kUpBytes)
+            e = hipErrorOutOfMemory;
+        if (e == hipSuccess) {
+            memcpy(h_stage + pos, red.data(), rb);
+            pos += rb;
+            e = upload(pos);
+        }
         if (e == hipSuccess)
             e = run_phase(sg);
         if (e == hipSuccess)
             e = run_phase(su);
         // 3. the norms of the new requests and the step norms, one readback
         if (e == hipSuccess && !red.empty()) {
-            ReduceItem *dev_ri =
-                (ReduceItem *)(stage_dev + kDescBytes + kItemBytes + kRedItemsOff);
-            char *hst = h_stage + kDescBytes + kItemBytes + kRedItemsOff;
-            memcpy(hst, red.data(), red.size() * sizeof(ReduceItem));
-            e = hipMemcpyAsync(dev_ri, hst, red.size() * sizeof(ReduceItem),
-                               hipMemcpyHostToDevice, stream);
-            if (e == hipSuccess)
-                e = launch_reduce_grouped(dev_ri, (int)red.size(), stream);
+            e = launch_reduce_grouped(dev_ri, (int)red.size(), stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(h_red, dev_d, red.size() * sizeof(double),
                                    hipMemcpyDeviceToHost, stream);
@@ -528,11 +530,11 @@ struct HipExec {
             add_problem(hs, r->plan.prec_h, 0, 0,
                         gram_desc(d->A, U, d->P, r->m, r->n, 1.0f, 0.0f, 1, r->plan.prec_h));
         }
-        size_t dpos = 0, ipos = 0;   // the tick's wait has passed: the area is free
+        size_t pos = 0;   // the tick's wait has passed: the region is free
         std::vector<Staged> sh;
-        hipError_t e = stage(hs, dpos, ipos, sh);
+        hipError_t e = stage(hs, pos, sh);
         if (e == hipSuccess)
-            e = upload(dpos, ipos);
+            e = upload(pos);
         if (e == hipSuccess)
             e = run_phase(sh);
         for (serve::Req *r : done) {
