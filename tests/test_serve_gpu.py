@@ -6,6 +6,7 @@
   footprint (a tight arena forces waiting, never overflow); the two size
   bands give the same bits as one band for all sizes;
 * every result meets the polar tolerances and matches the FP64 oracle's H;
+* many small requests in flight at once give the same bits for the same input;
 * error paths: non-finite input fails alone, too-large and queue-full are
   rejected at submit, unknown and twice-polled ids are reported.
 """
@@ -191,6 +192,45 @@ def test_tight_arena_admission(la):
     assert st["arena_high_water"] <= arena
     for i in ids:
         assert out[i][0] == la.Status.OK
+
+
+def test_many_small_requests_in_flight(la):
+    """1200 requests of 64 x 64 submitted back to back on 4096 slots, so that
+    each grouped launch holds dozens of problems laid out over the XCDs (with
+    empty padding items).  Every request completes, 30 copies of each of 40
+    inputs give the same bits wherever and whenever they ran, and each
+    distinct result meets the polar tolerances."""
+    distinct = [la_inputs.polar_case(64, 64, 10.0 ** -(1 + i % 4),
+                                     seeds=(970 + i, 1070 + i, 1170 + i)) for i in range(40)]
+    reps = 30
+    peak_active = 0
+    with la.Server(512 << 20, max_slots=4096) as srv:
+        ids = [srv.submit(distinct[k % 40].A32) for k in range(40 * reps)]
+        out = {}
+        t0 = time.time()
+        while len(out) < len(ids):
+            peak_active = max(peak_active, srv.stats()["active"])
+            for i in ids:
+                if i not in out:
+                    r = srv.poll(i)
+                    if r is not None:
+                        out[i] = r
+            assert time.time() - t0 < 100, f"{len(ids) - len(out)} requests pending"
+            time.sleep(0.001)
+        st = srv.stats()
+    print(st, "peak active", peak_active)
+    assert st["completed"] == len(ids) and st["failed"] == 0
+    for k, i in enumerate(ids):
+        status, U, H, info = out[i]
+        assert status == la.Status.OK
+        j = ids[k % 40]
+        assert np.array_equal(U, out[j][1]) and np.array_equal(H, out[j][2]), k
+    for c, i in zip(distinct, ids[:40]):
+        A = c.A32.astype(np.float64)
+        U64, H64 = out[i][1].astype(np.float64), out[i][2].astype(np.float64)
+        orth = np.linalg.norm(U64.T @ U64 - np.eye(64)) / 8.0
+        resid = np.linalg.norm(A - U64 @ H64) / np.linalg.norm(A)
+        assert orth <= TOL and resid <= TOL, (orth, resid)
 
 
 def test_error_paths(la):
